@@ -1,0 +1,183 @@
+"""Benchmark of the GLS grid on one MI355X.
+
+A step is one pass of the whole hot path over the paper-shape workload
+(n = 1000 samples, p = 4, m = 100,000 SNPs, t = 1,000 traits, synthetic data
+drawn by `synth`): rotation of every SNP by Z^T (FP64 MFMA GEMM) and the solve
+of the 10^8-problem grid (trait rotation, per-trait prologue, fused
+contraction + FP64 p x p solve), with b left in HBM. Inputs (genotypes as
+uint8, traits as FP64) are resident in HBM before timing starts; the host
+eigendecomposition of the kinship matrix is setup and is not timed.
+
+The headline value is the FP32 form's throughput (GLS problems/s); the FP64
+and split-BF16 forms are timed the same way and reported beside it, each with
+its fused kernel's fraction of the MFMA peak of its own precision. The
+oracle (plain FP64 C, dense Cholesky per problem) is timed on the host cores
+on a bounded sample as a reference point.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published dense peaks
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0}
+HBM_GBPS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, phi, xl, budget_s: float = 12.0):
+    """Time the oracle on a bounded sample of the workload: problems with distinct
+    traits, so that each pays its own O(n^3) factorisation (Table 1, LAPACK row)."""
+    import oracle
+
+    oracle.build(force=False)
+    threads = os.cpu_count() or 1
+    import synth
+
+    rng = np.random.default_rng(0)
+    count = threads
+    while True:
+        jj = rng.choice(w.t, size=min(count, w.t), replace=False)
+        ii = rng.choice(w.m, size=jj.size, replace=False)
+        y, h2 = synth.traits(w, 0, w.t)
+        xr = synth.snp_columns(w, ii)
+        t0 = time.perf_counter()
+        oracle.gls(phi, xl, xr, y[jj], h2[jj], nthreads=threads)
+        dt = time.perf_counter() - t0
+        if dt >= budget_s / 3 or jj.size >= w.t:
+            break
+        count = int(min(w.t, max(count * 2, count * budget_s / max(dt, 1e-3))))
+    return {"value": jj.size / dt, "unit": "GLS problems/s", "cores": threads, "kind": "oracle",
+            "sample": "%d problems (i, j) of the %s workload with distinct traits, each factorising "
+                      "its own n x n M_j; %.1f s on %d threads" % (jj.size, w.name, dt, threads)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="paper_m1e5")
+    ap.add_argument("--forms", default="f32,f64,bf16x3", help="headline form first")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the GLS grid shards along SNPs with no exchange, "
+              "and this build measures one GPU's share (use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_1210_7683_amd import costmodel as cm
+    from paper_1210_7683_amd import gwas
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    forms = args.forms.split(",")
+    w = synth.WORKLOADS[args.workload]
+    log("workload %s: n=%d p=%d m=%d t=%d" % (w.name, w.n, w.p, w.m, w.t))
+    t0 = time.perf_counter()
+    phi, xl = synth.kinship(w), synth.covariates(w)
+    xr = synth.snps(w)
+    y, h2 = synth.traits(w)
+    ev, z = np.linalg.eigh(phi)
+    log("inputs drawn and Phi eigendecomposed in %.1f s" % (time.perf_counter() - t0))
+
+    cohort = gwas.Cohort(z, ev, xl, w.m, forms=tuple(forms), timing=True)
+    xr_d = torch.from_numpy(xr).cuda()
+    y_d = torch.from_numpy(y).cuda()
+    torch.cuda.synchronize()
+    problems = w.m * w.t
+    flops_gls = cm.flops_per_gls_contraction(w.n, w.p)
+    results = {}
+    for form in forms:
+        dt = torch.float64 if form == "f64" else torch.float32
+        b = torch.empty((w.m, w.t, w.p), dtype=dt, device="cuda")
+
+        def step():
+            cohort.rotate(0, xr_d)
+            cohort.solve(y_d, h2, form=form, out=b)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        cohort.reset_stats()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        e0.record()
+        for _ in range(args.steps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        ms = e0.elapsed_time(e1) / args.steps
+        st = cohort.stats()
+        fused_ms = st["fused_ms"] / max(1, st["fused_launches"])
+        rot_ms = st["rotate_ms"] / max(1, st["rotate_launches"])
+        mult = 3 if form == "bf16x3" else 1          # three BF16 products per pair
+        achieved = mult * flops_gls * problems / (fused_ms * 1e-3) / 1e12
+        results[form] = {
+            "gls_per_s": problems / (ms * 1e-3),
+            "ms_per_step": ms,
+            "wall_ms_per_step": wall * 1e3 / args.steps,
+            "fused_ms": fused_ms,
+            "rotate_ms": rot_ms,
+            "solve_only_gls_per_s": problems / (fused_ms * 1e-3),
+            "fused_tflops": achieved,
+            "mfma_frac": achieved / PEAK_TFLOPS[form],
+            "non_spd": st["non_spd"],
+            "finite": bool(torch.isfinite(b).all()),
+        }
+        log("%s: %.3f ms/step (fused %.3f ms, rotate %.3f ms) -> %.3e GLS/s, fused %.1f TFLOP/s "
+            "= %.1f%% of %s peak" % (form, ms, fused_ms, rot_ms, results[form]["gls_per_s"],
+                                      achieved, 100 * achieved / PEAK_TFLOPS[form], form))
+        del b
+        torch.cuda.empty_cache()
+    cohort.close()
+
+    head = forms[0]
+    r = results[head]
+    mult = 3 if head == "bf16x3" else 1
+    line = {
+        "metric": "GLS problems solved/s + MFMA % of peak, FP64 vs FP32 vs split-BF16; p99",
+        "value": r["gls_per_s"],
+        "unit": "GLS problems/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f32", "f64": "f64", "bf16x3": "bf16x3"}[head],
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "p": w.p, "m": w.m, "t": w.t,
+                   "form": head, "step": "rotate all SNPs + solve the full grid, b in HBM"},
+        "roofline": {"bound": "mfma", "achieved": r["fused_tflops"], "peak": PEAK_TFLOPS[head],
+                     "unit": "TFLOP/s", "frac": r["mfma_frac"], "traffic": None,
+                     "kernel": "fused_kernel<%s, p=4>" % head,
+                     "flops_per_launch": mult * flops_gls * problems},
+        "forms": results,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample ...")
+        line["cpu_baseline"] = cpu_baseline(w, phi, xl)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,179 @@
+/*
+ * libgwas: the GLS grid of multi-trait GWAS on one AMD MI355X (gfx950).
+ *
+ * For every SNP i and trait j the library computes the generalized
+ * least-squares estimate of the paper's Section 2, Eq. (1),
+ *
+ *     b_ij = (X_i^T M_j^{-1} X_i)^{-1} X_i^T M_j^{-1} y_j,   X_i = [X_L | x_i],
+ *
+ * with the covariance of Eq. (2) without its scale factor,
+ * M_j = h2_j Phi + (1 - h2_j) I (b is invariant to the scale sigma2_j of M_j).
+ * It follows the paper's final algorithm (Section 3.2, Algorithm 5): Phi is
+ * given through its eigendecomposition Phi = Z diag(w) Z^T (computed by the
+ * caller in FP64), X_L, the SNPs and the traits are rotated once by Z^T, and
+ * every (i, j) problem then costs O(p n) work plus a p x p SPD solve.
+ *
+ * Conventions for every call
+ *   - n samples, p columns per design matrix (2 <= p <= 20, Section 3.3);
+ *   - matrices are column-major: Z is n x n (eigenvector k is the contiguous
+ *     column k), X_L is n x (p-1), a SNP block is n x mb (SNP-major: the n
+ *     genotypes of one SNP are contiguous), a trait block is n x tb;
+ *   - b is m x tb x p with p fastest: b[(i * tb + j) * p + q];
+ *   - "stream" is a hipStream_t passed as void* (NULL: the null stream); the
+ *     calls enqueue work and return; the caller synchronises that stream.
+ *     Calls on one context must be issued from one thread on one stream;
+ *   - the caller owns every buffer it passes; the library copies what it keeps
+ *     and owns the resident cohort (Z, w, rotated X_L and SNPs) and its scratch;
+ *     buffers handed to an enqueuing call (SNP blocks, Y, h2, b) must stay
+ *     valid and unmodified until that stream has completed the call's work;
+ *   - every call returns a gwas_status; on failure gwas_last_error() holds a
+ *     message (thread-local) and nothing has been enqueued unless stated.
+ */
+#ifndef GWAS_H
+#define GWAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gwas_status;
+#define GWAS_OK 0
+#define GWAS_EINVAL 1  /* bad argument: size, range, pointer, dtype, form */
+#define GWAS_ENOMEM 2  /* device or pinned-host allocation failed        */
+#define GWAS_EHIP 3    /* a HIP runtime call failed (message has the code) */
+#define GWAS_EBUSY 4   /* serving: no free slot or memory, try again       */
+#define GWAS_ESTATE 5  /* call not valid in the object's current state     */
+
+/* element types of SNP blocks handed to gwas_rotate */
+#define GWAS_DT_F64 0
+#define GWAS_DT_F32 1
+#define GWAS_DT_U8 2   /* genotype counts 0, 1, 2 (any byte value is taken as a number) */
+
+/* precision forms of the O(m t p n) contractions (the Gram assembly and the
+ * p x p solve are FP64 in every form) */
+#define GWAS_FORM_F64 0    /* FP64 operands, FP64 MFMA accumulation; b in FP64          */
+#define GWAS_FORM_F32 1    /* FP32 operands, FP32 MFMA accumulation; b in FP32          */
+#define GWAS_FORM_BF16X3 2 /* split BF16 operands x = hi + lo, hi*hi + hi*lo + lo*hi,
+                              FP32 MFMA accumulation; b in FP32                          */
+#define GWAS_FORM_BIT(f) (1u << (f))
+
+typedef struct gwas_ctx gwas_ctx;
+
+typedef struct gwas_options {
+    int64_t m_capacity;  /* SNPs the cohort holds (> 0)                                 */
+    uint32_t forms;      /* OR of GWAS_FORM_BIT(): rotated SNP copies kept resident;
+                            0 means all three                                         */
+    int32_t device;      /* HIP device ordinal; -1: the current device                 */
+    int32_t max_traits;  /* traits handled per internal trait sub-block; 0: 1024       */
+    int32_t slab_snps;   /* SNPs per D2H slab when b is host memory; 0: auto           */
+    int32_t f32_flush;   /* FP32 form: fold the FP32 accumulators into FP64 every
+                            this many K chunks of 16 samples (0: never)               */
+    int32_t timing;      /* nonzero: time every fused and rotation launch with HIP
+                            events on its stream (read back by gwas_stats)           */
+    int32_t reserved[8];
+} gwas_options;
+
+typedef struct gwas_stats_t {
+    int64_t non_spd;        /* problems whose S_ij was not numerically SPD (b = NaN)   */
+    int64_t snps_rotated;   /* SNP columns rotated so far                              */
+    int64_t problems;       /* (SNP, trait) problems solved so far                     */
+    int64_t bytes_h2d;      /* bytes the library copied host -> device                 */
+    int64_t bytes_d2h;      /* bytes the library copied device -> host                 */
+    int64_t resident_bytes; /* device memory held by the context                       */
+    int64_t fused_launches; /* timed launches of the fused kernel (timing option)        */
+    double fused_ms;        /* their summed duration, ms                                 */
+    int64_t rotate_launches;/* timed launches of the rotation kernel                     */
+    double rotate_ms;       /* their summed duration, ms                                 */
+    int64_t reserved[6];
+} gwas_stats_t;
+
+/* Fill *opt with defaults (m_capacity must still be set). */
+void gwas_default_options(gwas_options *opt);
+
+/*
+ * Create a context: upload the eigendecomposition of the kinship matrix and
+ * the covariates, rotate the covariates (Algorithm 5, preloop: X'_L = Z^T X_L,
+ * in FP64), and allocate the resident rotated-SNP store for m_capacity SNPs in
+ * each requested form.
+ *   ctx   out: the new context (NULL on failure)
+ *   n     samples, 1 <= n <= 16384
+ *   p     design width, 2 <= p <= 20 (X_L has p-1 columns; put the intercept there)
+ *   Z     host, n x n column-major, orthogonal eigenvectors of Phi
+ *   w     host, n eigenvalues of Phi, finite (gwas_solve requires
+ *         h2_j w_k + 1 - h2_j > 0 for every k, i.e. M_j SPD)
+ *   X_L   host, n x (p-1) column-major
+ *   opt   options (m_capacity required)
+ * Errors: GWAS_EINVAL (sizes, NULL pointers, non-finite Z, w or X_L),
+ * GWAS_ENOMEM, GWAS_EHIP. Synchronous.
+ */
+gwas_status gwas_setup(gwas_ctx **ctx, int32_t n, int32_t p, const double *Z, const double *w,
+                       const double *X_L, const gwas_options *opt);
+
+/*
+ * Rotate SNPs [m0, m0 + mb) into the resident store: X'_R = Z^T X_R
+ * (Algorithm 5, preloop), as an FP64 MFMA GEMM; the result is kept in every
+ * resident form (FP64; rounded to FP32; split to BF16 hi/lo with its square).
+ *   X_R        n x mb, SNP-major, element type dtype (GWAS_DT_*)
+ *   on_device  nonzero: X_R is device memory; zero: host memory (copied in
+ *              bounded chunks through a device staging buffer)
+ * Errors: GWAS_EINVAL (range beyond m_capacity, dtype, NULL), GWAS_EHIP.
+ */
+gwas_status gwas_rotate(gwas_ctx *ctx, int64_t m0, int64_t mb, const void *X_R, int32_t dtype,
+                        int32_t on_device, void *stream);
+
+/*
+ * Solve the grid of SNPs [i0, i0 + mi) x the tb traits of Y (Algorithm 5,
+ * loops): rotate the traits (y' = Z^T y, FP64), form the per-trait weights
+ * d_jk = 1 / (h2_j w_k + 1 - h2_j) and the trait-only quantities in FP64
+ * (S_TL_j, b_T_j and the Cholesky factor of S_TL_j), then, in one fused
+ * kernel per trait sub-block, the p+1 contractions of length n per (i, j)
+ * (S_BR, S_BL, b_B) in the chosen form and the FP64 p x p solve.
+ *   tb          traits in the block (1 <= tb)
+ *   Y           n x tb, column-major FP64 (device memory if y_on_device)
+ *   h2          host, tb values in [0, 1); h2 = 1 is accepted when min w > 0
+ *   form        GWAS_FORM_*; its SNP copy must be resident (gwas_options.forms)
+ *   b           mi x tb x p, FP64 for GWAS_FORM_F64 else FP32; device memory if
+ *               b_on_device, else host memory (pinned memory gives overlapped
+ *               copies: b is produced in SNP slabs into two device buffers and
+ *               copied out on a second stream while the next slab computes)
+ * A problem whose Gram matrix S_ij is not numerically SPD (the SNP column is,
+ * to the working precision, a combination of the covariates) gets b_ij = NaN
+ * and is counted in gwas_stats_t.non_spd.
+ * Errors: GWAS_EINVAL (range, tb, h2 out of range, form not resident),
+ * GWAS_EHIP. The SNPs in range must have been rotated before.
+ */
+gwas_status gwas_solve(gwas_ctx *ctx, int64_t i0, int64_t mi, int32_t tb, const double *Y,
+                       int32_t y_on_device, const double *h2, int32_t form, void *b,
+                       int32_t b_on_device, void *stream);
+
+/*
+ * Copy rotated SNP columns [i0, i0 + mi) out of the resident store, n values
+ * each (FP64 for GWAS_FORM_F64, FP32 for GWAS_FORM_F32), into dst (device
+ * memory if dst_on_device, else host; synchronous on stream for host).
+ * For inspection and tests. Errors: GWAS_EINVAL, GWAS_EHIP.
+ */
+gwas_status gwas_copy_rotated(gwas_ctx *ctx, int64_t i0, int64_t mi, int32_t form, void *dst,
+                              int32_t dst_on_device, void *stream);
+
+/* Counters of the context (synchronises the device to read them). */
+gwas_status gwas_stats(gwas_ctx *ctx, gwas_stats_t *out);
+
+/* Zero the counters and the timing record of the context (synchronises). */
+gwas_status gwas_reset_stats(gwas_ctx *ctx);
+
+/* Release the context and all its device memory (synchronises first). */
+void gwas_destroy(gwas_ctx *ctx);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *gwas_last_error(void);
+
+/* Library version string. */
+const char *gwas_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GWAS_H */

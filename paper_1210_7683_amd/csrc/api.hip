@@ -1,0 +1,505 @@
+// C ABI of libgwas: context, resident cohort, rotation, solve, streaming of b.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "gwas_internal.h"
+
+using namespace gw;
+
+namespace {
+
+thread_local std::string g_err;
+
+gwas_status fail(gwas_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(e_ == hipErrorOutOfMemory ? GWAS_ENOMEM : GWAS_EHIP, "%s: %s (%d)", \
+                        #expr, hipGetErrorString(e_), (int)e_);                           \
+    } while (0)
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct gwas_ctx {
+    int dev = 0;
+    int n = 0, n_pad = 0, p = 0;
+    int64_t m_cap = 0;       // SNPs the store holds
+    int64_t m_rows = 0;      // rows allocated per plane (>= m_cap)
+    uint32_t forms = 0;
+    int tcap = 0;            // traits per internal sub-block
+    int slab = 0;            // SNPs per D2H slab
+    int f32_flush = 0;
+    double w_min = 0.0;
+
+    double *Z = nullptr;     // [n_pad][n_pad]: row k = eigenvector k (zeros beyond n)
+    double *w = nullptr;     // [n_pad]
+    double *xlt = nullptr;   // [p-1][n_pad]
+    double *xr64 = nullptr;  // [m_rows][n_pad]
+    float *xr32 = nullptr;   // [m_rows][n_pad]
+    uint16_t *xrbf = nullptr;  // 4 planes [m_rows][n_pad]
+
+    double *y_in = nullptr;  // [tcap][n] staging of host traits
+    double *yt = nullptr;    // [tcap][n_pad]
+    double *h2 = nullptr;    // [tcap]
+    void *panels[3] = {nullptr, nullptr, nullptr};  // per form
+    double *fac = nullptr;   // [tcap][fac_stride]
+    unsigned long long *counters = nullptr;  // [0] non-SPD problems
+
+    void *stage = nullptr;   // rotation staging for host SNP blocks
+    size_t stage_bytes = 0;
+    void *bstage[2] = {nullptr, nullptr};
+    size_t bstage_bytes = 0;
+    hipStream_t side = nullptr;
+    hipEvent_t ev_done[2] = {nullptr, nullptr};   // slab computed
+    hipEvent_t ev_free[2] = {nullptr, nullptr};   // slab copied out
+    hipEvent_t ev_side = nullptr;
+
+    int64_t snps_rotated = 0, problems = 0, bytes_h2d = 0, bytes_d2h = 0, resident = 0;
+
+    // optional per-launch timing: event pairs recorded around launches
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> t_fused, t_rot, t_pool;
+};
+
+namespace {
+
+template <typename T>
+gwas_status dalloc(gwas_ctx *c, T **p, size_t bytes) {
+    void *v = nullptr;
+    hipError_t e = hipMalloc(&v, bytes ? bytes : 16);
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? GWAS_ENOMEM : GWAS_EHIP, "hipMalloc(%zu): %s", bytes,
+                    hipGetErrorString(e));
+    e = hipMemset(v, 0, bytes ? bytes : 16);
+    if (e != hipSuccess) return fail(GWAS_EHIP, "hipMemset: %s", hipGetErrorString(e));
+    *p = (T *)v;
+    c->resident += (int64_t)bytes;
+    return GWAS_OK;
+}
+
+hipError_t timed_begin(gwas_ctx *c, hipStream_t s, std::pair<hipEvent_t, hipEvent_t> &ev) {
+    if (!c->timing) return hipSuccess;
+    if (!c->t_pool.empty()) {
+        ev = c->t_pool.back();
+        c->t_pool.pop_back();
+    } else {
+        hipError_t e = hipEventCreate(&ev.first);
+        if (e == hipSuccess) e = hipEventCreate(&ev.second);
+        if (e != hipSuccess) return e;
+    }
+    return hipEventRecord(ev.first, s);
+}
+
+hipError_t timed_end(gwas_ctx *c, hipStream_t s, std::pair<hipEvent_t, hipEvent_t> &ev,
+                     std::vector<std::pair<hipEvent_t, hipEvent_t>> &list) {
+    if (!c->timing) return hipSuccess;
+    hipError_t e = hipEventRecord(ev.second, s);
+    list.push_back(ev);
+    return e;
+}
+
+double drain(gwas_ctx *c, std::vector<std::pair<hipEvent_t, hipEvent_t>> &list, int64_t &count) {
+    double tot = 0.0;
+    for (auto &ev : list) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev.first, ev.second) == hipSuccess) tot += ms;
+        c->t_pool.push_back(ev);
+    }
+    count = (int64_t)list.size();
+    list.clear();
+    return tot;
+}
+
+void release(gwas_ctx *c) {
+    if (!c) return;
+    hipSetDevice(c->dev);
+    hipDeviceSynchronize();
+    for (auto *lst : {&c->t_fused, &c->t_rot, &c->t_pool})
+        for (auto &ev : *lst) {
+            hipEventDestroy(ev.first);
+            hipEventDestroy(ev.second);
+        }
+    void *ptrs[] = {c->Z, c->w, c->xlt, c->xr64, c->xr32, c->xrbf, c->y_in, c->yt, c->h2,
+                    c->panels[0], c->panels[1], c->panels[2], c->fac, c->counters, c->stage,
+                    c->bstage[0], c->bstage[1]};
+    for (void *p : ptrs)
+        if (p) hipFree(p);
+    for (int i = 0; i < 2; ++i) {
+        if (c->ev_done[i]) hipEventDestroy(c->ev_done[i]);
+        if (c->ev_free[i]) hipEventDestroy(c->ev_free[i]);
+    }
+    if (c->ev_side) hipEventDestroy(c->ev_side);
+    if (c->side) hipStreamDestroy(c->side);
+    delete c;
+}
+
+bool all_finite(const double *v, size_t count) {
+    for (size_t i = 0; i < count; ++i)
+        if (!isfinite(v[i])) return false;
+    return true;
+}
+
+size_t elt_size(int form) { return form == GWAS_FORM_F64 ? 8 : (form == GWAS_FORM_F32 ? 4 : 2); }
+
+}  // namespace
+
+namespace gw {
+hipError_t launch_fused(int form, const FusedArgs &a, hipStream_t s) {
+    switch (form) {
+    case GWAS_FORM_F64: return launch_fused_f64(a, s);
+    case GWAS_FORM_F32: return launch_fused_f32(a, s);
+    case GWAS_FORM_BF16X3: return launch_fused_bf16(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+}  // namespace gw
+
+extern "C" {
+
+const char *gwas_last_error(void) { return g_err.c_str(); }
+
+const char *gwas_version(void) { return "libgwas 0.1 (gfx950)"; }
+
+void gwas_default_options(gwas_options *opt) {
+    if (!opt) return;
+    memset(opt, 0, sizeof *opt);
+    opt->forms = 0;
+    opt->device = -1;
+    opt->max_traits = 1024;
+    opt->slab_snps = 0;
+    opt->f32_flush = 0;
+}
+
+gwas_status gwas_setup(gwas_ctx **out, int32_t n, int32_t p, const double *Z, const double *w,
+                       const double *X_L, const gwas_options *opt) {
+    g_err.clear();
+    if (!out) return fail(GWAS_EINVAL, "ctx pointer is NULL");
+    *out = nullptr;
+    if (n < 1 || n > 16384) return fail(GWAS_EINVAL, "n = %d outside [1, 16384]", n);
+    if (p < 2 || p > 20) return fail(GWAS_EINVAL, "p = %d outside [2, 20]", p);
+    if (!Z || !w || !X_L || !opt) return fail(GWAS_EINVAL, "NULL input pointer");
+    if (opt->m_capacity <= 0) return fail(GWAS_EINVAL, "m_capacity must be positive");
+    if (opt->max_traits < 0 || opt->slab_snps < 0 || opt->f32_flush < 0)
+        return fail(GWAS_EINVAL, "negative option");
+    const uint32_t forms = opt->forms ? opt->forms : 7u;
+    if (forms & ~7u) return fail(GWAS_EINVAL, "unknown form bits 0x%x", forms);
+    if (!all_finite(Z, (size_t)n * n) || !all_finite(w, n) || !all_finite(X_L, (size_t)n * (p - 1)))
+        return fail(GWAS_EINVAL, "non-finite value in Z, w or X_L");
+
+    gwas_ctx *c = new gwas_ctx();
+    int dev = opt->device;
+    if (dev < 0) {
+        if (hipGetDevice(&dev) != hipSuccess) { delete c; return fail(GWAS_EHIP, "hipGetDevice failed"); }
+    }
+    c->dev = dev;
+    if (hipSetDevice(dev) != hipSuccess) { delete c; return fail(GWAS_EINVAL, "bad device %d", dev); }
+    c->n = n;
+    c->n_pad = (int)round_up(n, kPadN);
+    c->p = p;
+    c->m_cap = opt->m_capacity;
+    c->m_rows = round_up(opt->m_capacity, 256);
+    c->forms = forms;
+    c->tcap = opt->max_traits ? opt->max_traits : 1024;
+    c->f32_flush = opt->f32_flush;
+    c->timing = opt->timing != 0;
+    c->w_min = *std::min_element(w, w + n);
+
+    gwas_status st;
+    const int np = c->n_pad;
+#define TRY(x) do { if ((st = (x)) != GWAS_OK) { release(c); return st; } } while (0)
+    TRY(dalloc(c, &c->Z, sizeof(double) * np * np));
+    TRY(dalloc(c, &c->w, sizeof(double) * np));
+    TRY(dalloc(c, &c->xlt, sizeof(double) * (size_t)(p - 1) * np));
+    const size_t plane = (size_t)c->m_rows * np;
+    if (forms & GWAS_FORM_BIT(GWAS_FORM_F64)) TRY(dalloc(c, &c->xr64, sizeof(double) * plane));
+    if (forms & GWAS_FORM_BIT(GWAS_FORM_F32)) TRY(dalloc(c, &c->xr32, sizeof(float) * plane));
+    if (forms & GWAS_FORM_BIT(GWAS_FORM_BF16X3)) TRY(dalloc(c, &c->xrbf, sizeof(uint16_t) * 4 * plane));
+    TRY(dalloc(c, &c->y_in, sizeof(double) * (size_t)c->tcap * n));
+    TRY(dalloc(c, &c->yt, sizeof(double) * (size_t)c->tcap * np));
+    TRY(dalloc(c, &c->h2, sizeof(double) * (size_t)c->tcap));
+    for (int f = 0; f < 3; ++f)
+        if (forms & GWAS_FORM_BIT(f)) {
+            const size_t planes = (f == GWAS_FORM_BF16X3) ? 2 * (size_t)(p + 1) : (size_t)(p + 1);
+            TRY(dalloc(c, &c->panels[f], elt_size(f) * planes * c->tcap * np));
+        }
+    TRY(dalloc(c, &c->fac, sizeof(double) * (size_t)c->tcap * fac_stride(p)));
+    TRY(dalloc(c, &c->counters, sizeof(unsigned long long) * 4));
+    c->stage_bytes = (size_t)64 << 20;
+    TRY(dalloc(c, &c->stage, c->stage_bytes));
+
+    // upload Z (row k = eigenvector k, padded), w, X_L; rotate X_L in FP64
+    {
+        double *zh = (double *)calloc((size_t)np * np, sizeof(double));
+        if (!zh) { release(c); return fail(GWAS_ENOMEM, "host allocation"); }
+        for (int k = 0; k < n; ++k) memcpy(zh + (size_t)k * np, Z + (size_t)k * n, sizeof(double) * n);
+        hipError_t e = hipMemcpy(c->Z, zh, sizeof(double) * np * np, hipMemcpyHostToDevice);
+        free(zh);
+        if (e != hipSuccess) { release(c); return fail(GWAS_EHIP, "upload Z: %s", hipGetErrorString(e)); }
+        double *wh = (double *)malloc(sizeof(double) * np);
+        for (int k = 0; k < np; ++k) wh[k] = k < n ? w[k] : 1.0;
+        e = hipMemcpy(c->w, wh, sizeof(double) * np, hipMemcpyHostToDevice);
+        free(wh);
+        if (e != hipSuccess) { release(c); return fail(GWAS_EHIP, "upload w: %s", hipGetErrorString(e)); }
+        e = hipMemcpy(c->stage, X_L, sizeof(double) * (size_t)n * (p - 1), hipMemcpyHostToDevice);
+        if (e != hipSuccess) { release(c); return fail(GWAS_EHIP, "upload X_L: %s", hipGetErrorString(e)); }
+        RotOut ro{c->xlt, nullptr, nullptr, 0, 0, np};
+        e = launch_rotate(c->stage, GWAS_DT_F64, p - 1, n, n, c->Z, np, ro, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) { release(c); return fail(GWAS_EHIP, "rotate X_L: %s", hipGetErrorString(e)); }
+        c->bytes_h2d += (int64_t)sizeof(double) * ((int64_t)n * n + n + (int64_t)n * (p - 1));
+    }
+
+    // D2H streaming: two staging buffers for b slabs, a side stream, events
+    c->slab = opt->slab_snps ? opt->slab_snps : (int)std::min<int64_t>(c->m_rows, 65536);
+    c->bstage_bytes = (size_t)c->slab * c->tcap * p * sizeof(double);
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+        release(c); return fail(GWAS_EHIP, "stream creation failed");
+    }
+    for (int i = 0; i < 2; ++i) {
+        if (hipEventCreateWithFlags(&c->ev_done[i], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_free[i], hipEventDisableTiming) != hipSuccess) {
+            release(c); return fail(GWAS_EHIP, "event creation failed");
+        }
+    }
+    if (hipEventCreateWithFlags(&c->ev_side, hipEventDisableTiming) != hipSuccess) {
+        release(c); return fail(GWAS_EHIP, "event creation failed");
+    }
+#undef TRY
+    *out = c;
+    return GWAS_OK;
+}
+
+gwas_status gwas_rotate(gwas_ctx *c, int64_t m0, int64_t mb, const void *X, int32_t dtype,
+                        int32_t on_device, void *stream) {
+    g_err.clear();
+    if (!c) return fail(GWAS_EINVAL, "ctx is NULL");
+    if (m0 < 0 || mb < 0 || m0 + mb > c->m_cap)
+        return fail(GWAS_EINVAL, "SNP range [%lld, %lld) outside capacity %lld", (long long)m0,
+                    (long long)(m0 + mb), (long long)c->m_cap);
+    if (dtype != GWAS_DT_F64 && dtype != GWAS_DT_F32 && dtype != GWAS_DT_U8)
+        return fail(GWAS_EINVAL, "unknown dtype %d", dtype);
+    if (mb == 0) return GWAS_OK;
+    if (!X) return fail(GWAS_EINVAL, "X_R is NULL");
+    HIP_TRY(hipSetDevice(c->dev));
+    hipStream_t s = (hipStream_t)stream;
+    const size_t esz = dtype == GWAS_DT_F64 ? 8 : (dtype == GWAS_DT_F32 ? 4 : 1);
+    RotOut ro{c->xr64, c->xr32, c->xrbf, c->m_rows, 0, c->n_pad};
+    std::pair<hipEvent_t, hipEvent_t> ev{};
+    if (on_device) {
+        ro.row0 = m0;
+        HIP_TRY(timed_begin(c, s, ev));
+        HIP_TRY(launch_rotate(X, dtype, mb, c->n, c->n, c->Z, c->n_pad, ro, s));
+        HIP_TRY(timed_end(c, s, ev, c->t_rot));
+    } else {
+        const int64_t per = std::max<int64_t>(1, (int64_t)(c->stage_bytes / (esz * c->n)));
+        for (int64_t done = 0; done < mb; done += per) {
+            const int64_t cnt = std::min(per, mb - done);
+            const size_t bytes = (size_t)cnt * c->n * esz;
+            HIP_TRY(hipMemcpyAsync(c->stage, (const uint8_t *)X + (size_t)done * c->n * esz, bytes,
+                                   hipMemcpyHostToDevice, s));
+            ro.row0 = m0 + done;
+            HIP_TRY(timed_begin(c, s, ev));
+            HIP_TRY(launch_rotate(c->stage, dtype, cnt, c->n, c->n, c->Z, c->n_pad, ro, s));
+            HIP_TRY(timed_end(c, s, ev, c->t_rot));
+            c->bytes_h2d += (int64_t)bytes;
+        }
+    }
+    c->snps_rotated += mb;
+    return GWAS_OK;
+}
+
+gwas_status gwas_solve(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, const double *Y,
+                       int32_t y_on_device, const double *h2, int32_t form, void *b,
+                       int32_t b_on_device, void *stream) {
+    g_err.clear();
+    if (!c) return fail(GWAS_EINVAL, "ctx is NULL");
+    if (form < 0 || form > 2) return fail(GWAS_EINVAL, "unknown form %d", form);
+    if (!(c->forms & GWAS_FORM_BIT(form))) return fail(GWAS_EINVAL, "form %d is not resident", form);
+    if (i0 < 0 || mi < 0 || i0 + mi > c->m_cap)
+        return fail(GWAS_EINVAL, "SNP range [%lld, %lld) outside capacity %lld", (long long)i0,
+                    (long long)(i0 + mi), (long long)c->m_cap);
+    if (tb < 1) return fail(GWAS_EINVAL, "tb = %d must be >= 1", tb);
+    if (!Y || !h2 || (mi > 0 && !b)) return fail(GWAS_EINVAL, "NULL pointer");
+    for (int j = 0; j < tb; ++j) {
+        const double h = h2[j];
+        const bool in_range = (h >= 0.0 && h < 1.0) || (h == 1.0 && c->w_min > 0.0);
+        if (!isfinite(h) || !in_range || !(h * c->w_min + (1.0 - h) > 0.0))
+            return fail(GWAS_EINVAL, "h2[%d] = %g gives a covariance that is not SPD", j, h);
+    }
+    if (!y_on_device && !all_finite(Y, (size_t)tb * c->n))
+        return fail(GWAS_EINVAL, "non-finite value in Y");
+    if (mi == 0) return GWAS_OK;
+    HIP_TRY(hipSetDevice(c->dev));
+    hipStream_t s = (hipStream_t)stream;
+    const int p = c->p, np = c->n_pad;
+    const size_t besz = form == GWAS_FORM_F64 ? 8 : 4;
+
+    const void *a_base = form == GWAS_FORM_F64 ? (const void *)c->xr64
+                       : form == GWAS_FORM_F32 ? (const void *)c->xr32 : (const void *)c->xrbf;
+
+    for (int j0 = 0; j0 < tb; j0 += c->tcap) {
+        const int jb = std::min(c->tcap, tb - j0);
+        // traits: stage (host) and rotate y' = Z^T y in FP64
+        const double *ysrc = Y + (size_t)j0 * c->n;
+        if (!y_on_device) {
+            HIP_TRY(hipMemcpyAsync(c->y_in, ysrc, sizeof(double) * (size_t)jb * c->n,
+                                   hipMemcpyHostToDevice, s));
+            c->bytes_h2d += (int64_t)sizeof(double) * jb * c->n;
+            ysrc = c->y_in;
+        }
+        HIP_TRY(hipMemcpyAsync(c->h2, h2 + j0, sizeof(double) * jb, hipMemcpyHostToDevice, s));
+        RotOut ro{c->yt, nullptr, nullptr, 0, 0, np};
+        HIP_TRY(launch_rotate(ysrc, GWAS_DT_F64, jb, c->n, c->n, c->Z, np, ro, s));
+        PrepArgs pa{c->yt, c->h2, c->w, c->xlt, c->panels[form], c->fac, jb, c->n, np, p, c->tcap,
+                    fac_stride(p), form};
+        HIP_TRY(launch_prep(pa, s));
+
+        FusedArgs fa{};
+        fa.a = a_base;
+        fa.a_plane_rows = c->m_rows;
+        fa.panels = c->panels[form];
+        fa.tcap = c->tcap;
+        fa.fac = c->fac;
+        fa.fac_stride = fac_stride(p);
+        fa.tb = jb;
+        fa.n_pad = np;
+        fa.p = p;
+        fa.rank_rtol = kRankRtol[form];
+        fa.non_spd = c->counters;
+        fa.f32_flush = form == GWAS_FORM_F32 ? c->f32_flush : 0;
+
+        if (b_on_device) {
+            fa.i0 = i0;
+            fa.mi = mi;
+            fa.b = (uint8_t *)b + (size_t)j0 * p * besz;
+            fa.ldt = tb;
+            std::pair<hipEvent_t, hipEvent_t> ev{};
+            HIP_TRY(timed_begin(c, s, ev));
+            HIP_TRY(launch_fused(form, fa, s));
+            HIP_TRY(timed_end(c, s, ev, c->t_fused));
+        } else {
+            // slabs of SNPs into two device buffers; copies out on the side stream
+            if (!c->bstage[0]) {
+                for (int u = 0; u < 2; ++u) {
+                    hipError_t e = hipMalloc(&c->bstage[u], c->bstage_bytes);
+                    if (e != hipSuccess)
+                        return fail(GWAS_ENOMEM, "b staging (%zu bytes): %s", c->bstage_bytes,
+                                    hipGetErrorString(e));
+                    c->resident += (int64_t)c->bstage_bytes;
+                }
+            }
+            int slot = 0;
+            for (int64_t s0 = 0; s0 < mi; s0 += c->slab, slot ^= 1) {
+                const int64_t cnt = std::min<int64_t>(c->slab, mi - s0);
+                HIP_TRY(hipStreamWaitEvent(s, c->ev_free[slot], 0));
+                fa.i0 = i0 + s0;
+                fa.mi = cnt;
+                fa.b = c->bstage[slot];
+                fa.ldt = jb;
+                std::pair<hipEvent_t, hipEvent_t> ev{};
+                HIP_TRY(timed_begin(c, s, ev));
+                HIP_TRY(launch_fused(form, fa, s));
+                HIP_TRY(timed_end(c, s, ev, c->t_fused));
+                HIP_TRY(hipEventRecord(c->ev_done[slot], s));
+                HIP_TRY(hipStreamWaitEvent(c->side, c->ev_done[slot], 0));
+                const size_t row = (size_t)jb * p * besz;
+                HIP_TRY(hipMemcpy2DAsync((uint8_t *)b + ((size_t)s0 * tb + j0) * p * besz,
+                                         (size_t)tb * p * besz, c->bstage[slot], row, row, (size_t)cnt,
+                                         hipMemcpyDeviceToHost, c->side));
+                HIP_TRY(hipEventRecord(c->ev_free[slot], c->side));
+                c->bytes_d2h += (int64_t)(row * cnt);
+            }
+            HIP_TRY(hipEventRecord(c->ev_side, c->side));
+            HIP_TRY(hipStreamWaitEvent(s, c->ev_side, 0));
+        }
+    }
+    c->problems += mi * (int64_t)tb;
+    return GWAS_OK;
+}
+
+gwas_status gwas_copy_rotated(gwas_ctx *c, int64_t i0, int64_t mi, int32_t form, void *dst,
+                              int32_t dst_on_device, void *stream) {
+    g_err.clear();
+    if (!c) return fail(GWAS_EINVAL, "ctx is NULL");
+    if (form != GWAS_FORM_F64 && form != GWAS_FORM_F32)
+        return fail(GWAS_EINVAL, "copy_rotated supports the FP64 and FP32 stores only");
+    if (!(c->forms & GWAS_FORM_BIT(form))) return fail(GWAS_EINVAL, "form %d is not resident", form);
+    if (i0 < 0 || mi < 0 || i0 + mi > c->m_cap) return fail(GWAS_EINVAL, "SNP range outside capacity");
+    if (mi == 0) return GWAS_OK;
+    if (!dst) return fail(GWAS_EINVAL, "dst is NULL");
+    HIP_TRY(hipSetDevice(c->dev));
+    hipStream_t s = (hipStream_t)stream;
+    const size_t esz = form == GWAS_FORM_F64 ? 8 : 4;
+    const uint8_t *src = (const uint8_t *)(form == GWAS_FORM_F64 ? (void *)c->xr64 : (void *)c->xr32) +
+                         (size_t)i0 * c->n_pad * esz;
+    HIP_TRY(hipMemcpy2DAsync(dst, c->n * esz, src, c->n_pad * esz, c->n * esz, (size_t)mi,
+                             dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    if (!dst_on_device) HIP_TRY(hipStreamSynchronize(s));
+    return GWAS_OK;
+}
+
+gwas_status gwas_stats(gwas_ctx *c, gwas_stats_t *out) {
+    g_err.clear();
+    if (!c || !out) return fail(GWAS_EINVAL, "NULL pointer");
+    HIP_TRY(hipSetDevice(c->dev));
+    HIP_TRY(hipDeviceSynchronize());
+    unsigned long long cnt[4];
+    HIP_TRY(hipMemcpy(cnt, c->counters, sizeof cnt, hipMemcpyDeviceToHost));
+    memset(out, 0, sizeof *out);
+    out->non_spd = (int64_t)cnt[0];
+    out->snps_rotated = c->snps_rotated;
+    out->problems = c->problems;
+    out->bytes_h2d = c->bytes_h2d;
+    out->bytes_d2h = c->bytes_d2h;
+    out->resident_bytes = c->resident;
+    // timing record: kept until reset, so repeated queries see the same totals
+    double fms = 0.0, rms = 0.0;
+    for (auto &ev : c->t_fused) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev.first, ev.second) == hipSuccess) fms += ms;
+    }
+    for (auto &ev : c->t_rot) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev.first, ev.second) == hipSuccess) rms += ms;
+    }
+    out->fused_launches = (int64_t)c->t_fused.size();
+    out->fused_ms = fms;
+    out->rotate_launches = (int64_t)c->t_rot.size();
+    out->rotate_ms = rms;
+    return GWAS_OK;
+}
+
+gwas_status gwas_reset_stats(gwas_ctx *c) {
+    g_err.clear();
+    if (!c) return fail(GWAS_EINVAL, "NULL pointer");
+    HIP_TRY(hipSetDevice(c->dev));
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemset(c->counters, 0, sizeof(unsigned long long) * 4));
+    int64_t cnt;
+    drain(c, c->t_fused, cnt);
+    drain(c, c->t_rot, cnt);
+    c->snps_rotated = c->problems = c->bytes_h2d = c->bytes_d2h = 0;
+    return GWAS_OK;
+}
+
+void gwas_destroy(gwas_ctx *c) { release(c); }
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Internal declarations shared by the HIP sources of libgwas (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gwas.h"
+
+namespace gw {
+
+// Sample axis padding: rotated rows are stored with n_pad = round_up(n, 64)
+// values (zeros beyond n), so every K loop runs over whole 64-byte chunks.
+constexpr int kPadN = 64;
+// Bytes of one row that a K chunk of the fused kernel stages in LDS, and the
+// LDS row stride (16 bytes of padding keep 16-byte reads of 16 consecutive
+// rows on distinct banks).
+constexpr int kChunkBytes = 64;
+constexpr int kRowStride = kChunkBytes + 16;
+
+// Relative floor of the Schur pivot of the SNP column, per form: a problem
+// whose S_BR - |L^{-1} S_BL|^2 does not exceed this fraction of S_BR is
+// treated as rank-deficient (b = NaN). It scales with the contraction
+// precision: the pivot's computed value is noise below it.
+constexpr double kRankRtol[3] = {1e-10, 1e-4, 1e-3};
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Round-to-nearest-even of an FP32 value to BF16 (finite inputs), as raw bits.
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// x = hi + lo with hi = bf16(x) and lo = bf16(x - hi); x - hi is exact in FP32.
+__device__ __forceinline__ void bf16_split(float x, uint16_t &hi, uint16_t &lo) {
+    hi = bf16_rne(x);
+    lo = bf16_rne(x - bf16_to_f32(hi));
+}
+
+// Output planes of a rotation (any pointer may be null).
+struct RotOut {
+    double *f64;      // [rows][ld]
+    float *f32;       // [rows][ld]
+    uint16_t *bf;     // 4 planes, each [plane_rows][ld]: x hi, x lo, x^2 hi, x^2 lo
+    int64_t plane_rows;
+    int64_t row0;     // first output row
+    int ld;           // n_pad
+};
+
+// out[row0 + i][k] = sum_r X[i][r] Z[k][r]  for i < rows, k < n_pad (FP64 MFMA).
+hipError_t launch_rotate(const void *X, int dtype, int64_t rows, int n, int64_t ldx,
+                         const double *Zrows, int n_pad, const RotOut &out, hipStream_t s);
+
+// Per-trait prologue (FP64): weights, contraction panels, and the factor of S_TL.
+struct PrepArgs {
+    const double *yt;    // [tb][n_pad] rotated traits
+    const double *h2;    // [tb]
+    const double *w;     // [n_pad]
+    const double *xlt;   // [p-1][n_pad] rotated covariates
+    void *panels;        // form layout, plane stride tcap rows
+    double *fac;         // [tb][fac_stride]: packed L^{-1} (lower), then z = L^{-1} b_T
+    int tb, n, n_pad, p, tcap, fac_stride, form;
+};
+hipError_t launch_prep(const PrepArgs &a, hipStream_t s);
+
+inline int fac_stride(int p) {
+    int q = p - 1;
+    int v = q * (q + 1) / 2 + q;
+    return (v + 1) & ~1;
+}
+
+// Fused contraction + solve.
+struct FusedArgs {
+    const void *a;          // resident rotated SNP planes (form layout), rows of n_pad
+    int64_t a_plane_rows;   // rows per plane (bf16 form has 4 planes)
+    int64_t i0, mi;         // SNP range
+    const void *panels;     // trait panels, plane stride tcap rows
+    int tcap;
+    const double *fac;      // [tb][fac_stride]
+    int fac_stride;
+    int tb;                 // traits in this sub-block
+    int n_pad, p;
+    void *b;                // output: b[(i - i0) * ldt + j] * p ...
+    int64_t ldt;            // trait stride of b (in problems)
+    double rank_rtol;
+    unsigned long long *non_spd;
+    int f32_flush;
+};
+hipError_t launch_fused(int form, const FusedArgs &a, hipStream_t s);
+hipError_t launch_fused_f64(const FusedArgs &a, hipStream_t s);
+hipError_t launch_fused_f32(const FusedArgs &a, hipStream_t s);
+hipError_t launch_fused_bf16(const FusedArgs &a, hipStream_t s);
+
+}  // namespace gw

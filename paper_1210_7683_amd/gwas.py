@@ -1,0 +1,242 @@
+"""ctypes binding of libgwas (include/gwas.h): argument marshalling only.
+
+Every step of the computation runs in the library's HIP kernels. PyTorch is
+used for device memory (tensors) and streams. Loading fails loudly when the
+library has not been built; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgwas.so")
+
+OK, EINVAL, ENOMEM, EHIP, EBUSY, ESTATE = 0, 1, 2, 3, 4, 5
+DT_F64, DT_F32, DT_U8 = 0, 1, 2
+FORM_F64, FORM_F32, FORM_BF16X3 = 0, 1, 2
+FORMS = {"f64": FORM_F64, "f32": FORM_F32, "bf16x3": FORM_BF16X3}
+
+_lib = None
+
+
+class GwasError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("libgwas status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("m_capacity", ctypes.c_int64), ("forms", ctypes.c_uint32),
+                ("device", ctypes.c_int32), ("max_traits", ctypes.c_int32),
+                ("slab_snps", ctypes.c_int32), ("f32_flush", ctypes.c_int32),
+                ("timing", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("non_spd", ctypes.c_int64), ("snps_rotated", ctypes.c_int64),
+                ("problems", ctypes.c_int64), ("bytes_h2d", ctypes.c_int64),
+                ("bytes_d2h", ctypes.c_int64), ("resident_bytes", ctypes.c_int64),
+                ("fused_launches", ctypes.c_int64), ("fused_ms", ctypes.c_double),
+                ("rotate_launches", ctypes.c_int64), ("rotate_ms", ctypes.c_double),
+                ("reserved", ctypes.c_int64 * 6)]
+
+
+def load():
+    """Load libgwas.so (raises if it is missing: build it with paper_1210_7683_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libgwas.so is not built (%s); run python -m paper_1210_7683_amd.build"
+                          % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.gwas_default_options.argtypes = [ctypes.POINTER(Options)]
+    lib.gwas_default_options.restype = None
+    lib.gwas_setup.argtypes = [ctypes.POINTER(vp), i32, i32, vp, vp, vp, ctypes.POINTER(Options)]
+    lib.gwas_setup.restype = i32
+    lib.gwas_rotate.argtypes = [vp, i64, i64, vp, i32, i32, vp]
+    lib.gwas_rotate.restype = i32
+    lib.gwas_solve.argtypes = [vp, i64, i64, i32, vp, i32, vp, i32, vp, i32, vp]
+    lib.gwas_solve.restype = i32
+    lib.gwas_copy_rotated.argtypes = [vp, i64, i64, i32, vp, i32, vp]
+    lib.gwas_copy_rotated.restype = i32
+    lib.gwas_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    lib.gwas_stats.restype = i32
+    lib.gwas_reset_stats.argtypes = [vp]
+    lib.gwas_reset_stats.restype = i32
+    lib.gwas_destroy.argtypes = [vp]
+    lib.gwas_destroy.restype = None
+    lib.gwas_last_error.argtypes = []
+    lib.gwas_last_error.restype = ctypes.c_char_p
+    lib.gwas_version.argtypes = []
+    lib.gwas_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st != OK:
+        raise GwasError(st, load().gwas_last_error().decode())
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _is_device(x) -> bool:
+    try:
+        import torch
+        return isinstance(x, torch.Tensor) and x.is_cuda
+    except ImportError:
+        return False
+
+
+def _ptr(x):
+    """(pointer, on_device, keepalive) of a numpy array or torch tensor."""
+    import torch
+    if isinstance(x, torch.Tensor):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return ctypes.c_void_p(x.data_ptr()), int(x.is_cuda), x
+    a = np.ascontiguousarray(x)
+    return ctypes.c_void_p(a.ctypes.data), 0, a
+
+
+_DT = {np.dtype(np.float64): DT_F64, np.dtype(np.float32): DT_F32, np.dtype(np.uint8): DT_U8}
+
+
+def _dtype_code(x) -> int:
+    import torch
+    if isinstance(x, torch.Tensor):
+        m = {torch.float64: DT_F64, torch.float32: DT_F32, torch.uint8: DT_U8}
+        if x.dtype not in m:
+            raise ValueError("unsupported dtype %s" % x.dtype)
+        return m[x.dtype]
+    d = np.asarray(x).dtype
+    if d not in _DT:
+        raise ValueError("unsupported dtype %s" % d)
+    return _DT[d]
+
+
+class Cohort:
+    """A resident cohort on one GPU: Z, w, rotated X_L and rotated SNPs.
+
+    Z [n][n] array whose column k is eigenvector k of Phi (numpy.linalg.eigh
+    output), w [n] eigenvalues, xl [(p-1)][n] covariate columns.
+    """
+
+    def __init__(self, Z, w, xl, m_capacity: int, forms=("f64", "f32", "bf16x3"),
+                 max_traits: int = 1024, device: int = 0, slab_snps: int = 0, f32_flush: int = 0,
+                 timing: bool = False):
+        lib = load()
+        Z = np.asarray(Z, dtype=np.float64)
+        n = Z.shape[0]
+        # column-major n x n: column k contiguous
+        zc = np.ascontiguousarray(Z.T)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        xl = np.ascontiguousarray(np.atleast_2d(xl), dtype=np.float64)
+        if Z.shape != (n, n) or w.shape != (n,) or xl.shape[1] != n:
+            raise ValueError("inconsistent shapes")
+        opt = Options()
+        lib.gwas_default_options(ctypes.byref(opt))
+        opt.m_capacity = int(m_capacity)
+        opt.forms = sum(1 << FORMS[f] for f in forms)
+        opt.device = int(device)
+        opt.max_traits = int(max_traits)
+        opt.slab_snps = int(slab_snps)
+        opt.f32_flush = int(f32_flush)
+        opt.timing = int(bool(timing))
+        h = ctypes.c_void_p()
+        _check(lib.gwas_setup(ctypes.byref(h), n, xl.shape[0] + 1, zc.ctypes.data, w.ctypes.data,
+                              xl.ctypes.data, ctypes.byref(opt)))
+        self._h = h
+        self.n, self.p, self.m_capacity = n, xl.shape[0] + 1, int(m_capacity)
+        self.forms = tuple(forms)
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().gwas_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def rotate(self, m0: int, xr, stream=None):
+        """Rotate SNP columns xr [mb][n] (uint8, float32 or float64; numpy or torch) into [m0, m0+mb)."""
+        ptr, dev, keep = _ptr(xr)
+        mb = int(xr.shape[0]) if len(xr.shape) == 2 else 0
+        if mb and int(xr.shape[1]) != self.n:
+            raise ValueError("SNP block must be [mb][n]")
+        _check(load().gwas_rotate(self._h, int(m0), mb, ptr, _dtype_code(xr), dev, _stream_ptr(stream)))
+        if not dev:
+            self._sync(stream)
+        return keep
+
+    def solve(self, y, h2, form: str = "f32", i0: int = 0, m: int | None = None, out=None,
+              stream=None):
+        """b [m][t][p] for SNPs [i0, i0+m) and traits y [t][n] with heritabilities h2 [t].
+
+        out: a preallocated torch tensor (device or pinned host) or None (a new
+        device tensor). Enqueued on `stream` (default: torch's current stream).
+        """
+        import torch
+        lib = load()
+        f = FORMS[form]
+        m = self.m_capacity - i0 if m is None else int(m)
+        t = int(y.shape[0])
+        h2 = np.ascontiguousarray(h2, dtype=np.float64)
+        if h2.shape != (t,):
+            raise ValueError("h2 needs one value per trait")
+        yp, ydev, ykeep = _ptr(y if _is_device(y) else np.ascontiguousarray(y, dtype=np.float64))
+        if _is_device(y) and y.dtype != torch.float64:
+            raise ValueError("device traits must be float64")
+        dt = torch.float64 if f == FORM_F64 else torch.float32
+        if out is None:
+            out = torch.empty((m, t, self.p), dtype=dt, device="cuda:%d" % self.device)
+        if out.dtype != dt or tuple(out.shape) != (m, t, self.p) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous %s tensor of shape %s" % (dt, (m, t, self.p)))
+        _check(lib.gwas_solve(self._h, int(i0), m, t, yp, ydev, h2.ctypes.data, f,
+                              ctypes.c_void_p(out.data_ptr()), int(out.is_cuda), _stream_ptr(stream)))
+        self._keep = (ykeep, h2)
+        return out
+
+    def copy_rotated(self, i0: int, m: int, form: str = "f64"):
+        """Rotated SNP columns [i0, i0+m) from the resident store (numpy, [m][n])."""
+        f = FORMS[form]
+        out = np.empty((m, self.n), dtype=np.float64 if f == FORM_F64 else np.float32)
+        _check(load().gwas_copy_rotated(self._h, int(i0), int(m), f, out.ctypes.data, 0,
+                                        _stream_ptr(None)))
+        return out
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(load().gwas_stats(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats._fields_ if k != "reserved"}
+
+    def reset_stats(self):
+        _check(load().gwas_reset_stats(self._h))
+
+    def _sync(self, stream):
+        import torch
+        (stream or torch.cuda.current_stream()).synchronize()
+
+
+def version() -> str:
+    return load().gwas_version().decode()

@@ -1,0 +1,193 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Every test here runs the kernels on cuda:0 and compares b element by element
+with the oracle (oracle/oracle.c, a dense-Cholesky solve of Eq. (1)) on the
+same seeded inputs, to the per-form bound of the relative error of b_ij:
+FP64 1e-10, FP32 1e-5, split BF16 2e-3 (its measured bound, stated).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_common import TOL, cohort, rel_err
+
+pytestmark = pytest.mark.gpu
+
+FORMS = ["f64", "f32", "bf16x3"]
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def tiny(torch_cuda):
+    w = synth.WORKLOADS["tiny"]
+    phi, xl = synth.kinship(w), synth.covariates(w)
+    xr = synth.snps(w)
+    y, h2 = synth.traits(w)
+    ref = oracle.gls_grid(phi, xl, xr, y, h2)
+    c = cohort(phi, xl, xr)
+    yield dict(phi=phi, xl=xl, xr=xr, y=y, h2=h2, ref=ref, c=c)
+    c.close()
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_tiny_full_grid(tiny, form, torch_cuda):
+    b = tiny["c"].solve(tiny["y"], tiny["h2"], form=form).cpu().numpy()
+    err = rel_err(b, tiny["ref"])
+    print("tiny %s: max %.3e median %.3e" % (form, err.max(), np.median(err)))
+    assert b.shape == (512, 8, 4)
+    assert np.isfinite(b).all()
+    assert err.max() <= TOL[form]
+
+
+def test_rotation_matches_fp64_gemm(tiny, torch_cuda):
+    w, z = np.linalg.eigh(tiny["phi"])
+    xr = tiny["xr"]
+    ref = xr.astype(np.float64) @ z          # row i = (Z^T x_i)^T
+    got = tiny["c"].copy_rotated(0, xr.shape[0], "f64")
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    got32 = tiny["c"].copy_rotated(0, xr.shape[0], "f32")
+    assert np.array_equal(got32, got.astype(np.float32))
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32, np.uint8])
+def test_rotate_dtypes_and_device_input(tiny, dtype, torch_cuda):
+    torch = torch_cuda
+    xr = tiny["xr"][:100].astype(dtype)
+    w, z = np.linalg.eigh(tiny["phi"])
+    from paper_1210_7683_amd import gwas
+    c = gwas.Cohort(z, w, tiny["xl"], 300, forms=("f64",))
+    c.rotate(7, xr)                                   # host block
+    c.rotate(150, torch.from_numpy(xr).cuda())        # device block
+    torch.cuda.synchronize()
+    a = c.copy_rotated(7, 100, "f64")
+    b = c.copy_rotated(150, 100, "f64")
+    assert np.array_equal(a, b)
+    ref = xr.astype(np.float64) @ z
+    assert np.abs(a - ref).max() <= 1e-12 * np.abs(ref).max()
+    c.close()
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("n,p,m,t", [(200, 2, 333, 37), (77, 3, 100, 5), (130, 5, 129, 17),
+                                     (96, 8, 70, 33), (64, 13, 40, 9), (150, 20, 35, 18)])
+def test_ragged_shapes_and_p(form, n, p, m, t, torch_cuda):
+    phi, xl, xr, y, h2 = synth.small(n, p, m, t, seed=n * 31 + p)
+    ref = oracle.gls_grid(phi, xl, xr, y, h2)
+    c = cohort(phi, xl, xr, forms=(form,))
+    b = c.solve(y, h2, form=form).cpu().numpy()
+    c.close()
+    err = rel_err(b, ref)
+    print("n=%d p=%d m=%d t=%d %s: max %.3e" % (n, p, m, t, form, err.max()))
+    assert err.max() <= TOL[form]
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_subranges_and_trait_subblocks_are_bitwise_consistent(form, torch_cuda):
+    torch = torch_cuda
+    phi, xl, xr, y, h2 = synth.small(160, 4, 300, 70, seed=5)
+    c = cohort(phi, xl, xr, forms=(form,), max_traits=32)
+    full = c.solve(y, h2, form=form).cpu().numpy()          # three trait sub-blocks
+    part = c.solve(y, h2, form=form, i0=37, m=150).cpu().numpy()
+    assert np.array_equal(part, full[37:187])
+    ysub = c.solve(y[5:20], h2[5:20], form=form).cpu().numpy()
+    assert np.array_equal(ysub, full[:, 5:20])
+    ydev = c.solve(torch.from_numpy(y).cuda(), h2, form=form).cpu().numpy()
+    assert np.array_equal(ydev, full)
+    c.close()
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_host_output_streamed_in_slabs_equals_device_output(form, torch_cuda):
+    torch = torch_cuda
+    phi, xl, xr, y, h2 = synth.small(128, 4, 1000, 40, seed=9)
+    c = cohort(phi, xl, xr, forms=(form,), slab_snps=96, max_traits=16)
+    dev = c.solve(y, h2, form=form).cpu().numpy()
+    dt = torch.float64 if form == "f64" else torch.float32
+    host = torch.empty((1000, 40, 4), dtype=dt, pin_memory=True)
+    c.solve(y, h2, form=form, out=host)
+    torch.cuda.synchronize()
+    assert np.array_equal(host.numpy(), dev)
+    st = c.stats()
+    assert st["bytes_d2h"] == host.numel() * host.element_size()
+    c.close()
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_rank_deficient_snps_give_nan_and_are_counted(form, torch_cuda):
+    phi, xl, xr, y, h2 = synth.small(128, 4, 20, 6, seed=2)
+    cols = xr.astype(np.float64)
+    cols[3] = 2.0                      # monomorphic: a multiple of the intercept
+    cols[11] = xl[1]                   # a copy of a covariate
+    c = cohort(phi, xl, cols, forms=(form,))
+    b = c.solve(y, h2, form=form).cpu().numpy()
+    assert np.isnan(b[[3, 11]]).all()
+    ok = np.setdiff1d(np.arange(20), [3, 11])
+    assert np.isfinite(b[ok]).all()
+    assert c.stats()["non_spd"] == 2 * 6
+    ref = oracle.gls_grid(phi, xl, cols[ok], y, h2)
+    assert rel_err(b[ok], ref).max() <= TOL[form]
+    c.close()
+
+
+def test_errors_are_reported(torch_cuda):
+    from paper_1210_7683_amd import gwas
+    phi, xl, xr, y, h2 = synth.small(64, 4, 10, 3, seed=1)
+    w, z = np.linalg.eigh(phi)
+    with pytest.raises(gwas.GwasError) as e:
+        gwas.Cohort(z, w, np.vstack([xl] * 7), 10)          # p = 22
+    assert e.value.status == gwas.EINVAL
+    c = gwas.Cohort(z, w, xl, 10, forms=("f32",))
+    c.rotate(0, xr)
+    for bad in [np.full(3, 1.5), np.array([0.2, -0.1, 0.3]), np.array([0.2, np.nan, 0.3])]:
+        with pytest.raises(gwas.GwasError) as e:
+            c.solve(y, bad, form="f32")
+        assert e.value.status == gwas.EINVAL
+    with pytest.raises(gwas.GwasError):
+        c.solve(y, h2, form="f64")                          # form not resident
+    with pytest.raises(gwas.GwasError):
+        c.solve(y, h2, form="f32", i0=5, m=6)               # beyond capacity
+    with pytest.raises(gwas.GwasError):
+        c.rotate(8, xr[:5])
+    assert c.solve(y, h2, form="f32", m=0).shape == (0, 3, 4)
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def paper_m1e5(torch_cuda):
+    """The paper-shape workload (n = 1000, p = 4, m = 1e5, t = 1000) resident on the GPU."""
+    torch = torch_cuda
+    w = synth.WORKLOADS["paper_m1e5"]
+    phi, xl = synth.kinship(w), synth.covariates(w)
+    xr = synth.snps(w)
+    y, h2 = synth.traits(w)
+    ev, z = np.linalg.eigh(phi)
+    from paper_1210_7683_amd import gwas
+    c = gwas.Cohort(z, ev, xl, w.m)
+    c.rotate(0, torch.from_numpy(xr).cuda())
+    yd = torch.from_numpy(y).cuda()
+    yield dict(w=w, phi=phi, xl=xl, y=y, h2=h2, c=c, yd=yd)
+    c.close()
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_paper_shape_sampled_against_oracle(paper_m1e5, form, torch_cuda):
+    d = paper_m1e5
+    b = d["c"].solve(d["yd"], d["h2"], form=form)
+    ii, jj = synth.sample_problems(d["w"], 2000, salt=1)
+    keep = np.isin(jj, np.unique(jj)[:6])              # six traits keep the oracle to seconds
+    ii, jj = ii[keep][:120], jj[keep][:120]
+    got = b[ii, jj].cpu().numpy()
+    uj, inv = np.unique(jj, return_inverse=True)
+    ref = oracle.gls(d["phi"], d["xl"], synth.snp_columns(d["w"], ii), d["y"][uj], d["h2"][uj],
+                     trait=inv)
+    err = rel_err(got, ref)
+    print("paper_m1e5 %s sampled %d: max %.3e median %.3e" % (form, err.size, err.max(), np.median(err)))
+    assert err.max() <= TOL[form]
+    assert bool(torch_cuda.isfinite(b).all())
