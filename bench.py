@@ -72,6 +72,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="paper_m1e5")
     ap.add_argument("--forms", default="f32,f64,bf16x3", help="headline form first")
+    ap.add_argument("--f32-flush", type=int, default=None,
+                    help="FP32 form: FP64 fold interval in chunks of 16 samples (library default 2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -96,7 +98,7 @@ def main():
     ev, z = np.linalg.eigh(phi)
     log("inputs drawn and Phi eigendecomposed in %.1f s" % (time.perf_counter() - t0))
 
-    cohort = gwas.Cohort(z, ev, xl, w.m, forms=tuple(forms), timing=True)
+    cohort = gwas.Cohort(z, ev, xl, w.m, forms=tuple(forms), timing=True, f32_flush=args.f32_flush)
     xr_d = torch.from_numpy(xr).cuda()
     y_d = torch.from_numpy(y).cuda()
     torch.cuda.synchronize()

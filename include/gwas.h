@@ -70,7 +70,7 @@ typedef struct gwas_options {
     int32_t max_traits;  /* traits handled per internal trait sub-block; 0: 1024       */
     int32_t slab_snps;   /* SNPs per D2H slab when b is host memory; 0: auto           */
     int32_t f32_flush;   /* FP32 form: fold the FP32 accumulators into FP64 every
-                            this many K chunks of 16 samples (0: never)               */
+                            this many K chunks of 16 samples (0: never; default 2)    */
     int32_t timing;      /* nonzero: time every fused and rotation launch with HIP
                             events on its stream (read back by gwas_stats)           */
     int32_t reserved[8];
@@ -157,6 +157,25 @@ gwas_status gwas_solve(gwas_ctx *ctx, int64_t i0, int64_t mi, int32_t tb, const 
  */
 gwas_status gwas_copy_rotated(gwas_ctx *ctx, int64_t i0, int64_t mi, int32_t form, void *dst,
                               int32_t dst_on_device, void *stream);
+
+/*
+ * Copy an internal buffer of the most recent gwas_solve (or of the cohort) to
+ * host memory, for inspection and tests (synchronises the device):
+ *   GWAS_DBG_XL      rotated covariates X'_L: (p-1) x n_pad FP64 (n_pad = n
+ *                    rounded up to 64, zeros beyond n)
+ *   GWAS_DBG_YT      rotated traits y' of the last trait sub-block: tcap x n_pad FP64
+ *   GWAS_DBG_FAC     per-trait factors of the last sub-block: tcap x S FP64 with
+ *                    S = even(q(q+1)/2 + q), q = p-1: packed L_j^{-1} (row-major
+ *                    lower), then z_j = L_j^{-1} b_T_j
+ *   GWAS_DBG_PANELS  trait panels of the last sub-block in the form's layout
+ * bytes must equal the buffer's size (gwas_debug_size reports it).
+ */
+#define GWAS_DBG_XL 0
+#define GWAS_DBG_YT 1
+#define GWAS_DBG_FAC 2
+#define GWAS_DBG_PANELS 3
+int64_t gwas_debug_size(gwas_ctx *ctx, int32_t what, int32_t form);
+gwas_status gwas_debug_copy(gwas_ctx *ctx, int32_t what, int32_t form, void *dst, int64_t bytes);
 
 /* Counters of the context (synchronises the device to read them). */
 gwas_status gwas_stats(gwas_ctx *ctx, gwas_stats_t *out);

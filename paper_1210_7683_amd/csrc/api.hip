@@ -185,7 +185,7 @@ void gwas_default_options(gwas_options *opt) {
     opt->device = -1;
     opt->max_traits = 1024;
     opt->slab_snps = 0;
-    opt->f32_flush = 0;
+    opt->f32_flush = 2;
 }
 
 gwas_status gwas_setup(gwas_ctx **out, int32_t n, int32_t p, const double *Z, const double *w,
@@ -497,6 +497,33 @@ gwas_status gwas_reset_stats(gwas_ctx *c) {
     drain(c, c->t_fused, cnt);
     drain(c, c->t_rot, cnt);
     c->snps_rotated = c->problems = c->bytes_h2d = c->bytes_d2h = 0;
+    return GWAS_OK;
+}
+
+int64_t gwas_debug_size(gwas_ctx *c, int32_t what, int32_t form) {
+    if (!c) return -1;
+    const int64_t np = c->n_pad;
+    switch (what) {
+    case GWAS_DBG_XL: return (int64_t)sizeof(double) * (c->p - 1) * np;
+    case GWAS_DBG_YT: return (int64_t)sizeof(double) * c->tcap * np;
+    case GWAS_DBG_FAC: return (int64_t)sizeof(double) * c->tcap * fac_stride(c->p);
+    case GWAS_DBG_PANELS:
+        if (form < 0 || form > 2 || !(c->forms & GWAS_FORM_BIT(form))) return -1;
+        return (int64_t)elt_size(form) * (form == GWAS_FORM_BF16X3 ? 2 : 1) * (c->p + 1) * c->tcap * np;
+    default: return -1;
+    }
+}
+
+gwas_status gwas_debug_copy(gwas_ctx *c, int32_t what, int32_t form, void *dst, int64_t bytes) {
+    g_err.clear();
+    const int64_t need = gwas_debug_size(c, what, form);
+    if (need < 0 || !dst || bytes != need) return fail(GWAS_EINVAL, "bad debug request");
+    const void *src = what == GWAS_DBG_XL ? (const void *)c->xlt
+                    : what == GWAS_DBG_YT ? (const void *)c->yt
+                    : what == GWAS_DBG_FAC ? (const void *)c->fac : c->panels[form];
+    HIP_TRY(hipSetDevice(c->dev));
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(dst, src, (size_t)bytes, hipMemcpyDeviceToHost));
     return GWAS_OK;
 }
 

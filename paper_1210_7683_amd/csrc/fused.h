@@ -39,7 +39,7 @@ struct FusedCfg {
     static constexpr int FM = (FORM == GWAS_FORM_BF16X3) ? (P <= 4 ? 2 : 1) : (P <= 9 ? 2 : 1);
     static constexpr int FN = (FORM == GWAS_FORM_BF16X3) ? 1
                             : (FORM == GWAS_FORM_F64)    ? (P <= 4 ? 2 : 1)
-                            : (FLUSH ? 1 : (P <= 9 ? 2 : 1));
+                            : (FLUSH ? (P <= 4 ? 2 : 1) : (P <= 9 ? 2 : 1));
     static constexpr int NT = 64 * WM * WN;
     static constexpr int TM = WM * FM * 16;
     static constexpr int TN = WN * FN * 16;
@@ -275,7 +275,7 @@ __global__ __launch_bounds__((FusedCfg<FORM, P, FLUSH>::NT)) void fused_kernel(F
             for (int u = 0; u < Q; ++u) z[u] = F[NTL + u];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t i = m_base + wm * FM * 16 + x * 16 + 4 * g + r;
+                const int64_t i = m_base + wm * FM * 16 + x * 16 + mfma16_row<FORM == GWAS_FORM_F64>(g, r);
                 if (i >= a.mi) continue;
                 double cq[NQ];
 #pragma unroll

@@ -27,6 +27,13 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
+// Row of a 16x16 MFMA result held in register r of a lane in lane group g
+// (= lane / 16); the column is lane % 16. The FP64 16x16x4 variant interleaves
+// its four rows (g, g+4, g+8, g+12); the FP32 and BF16 variants hold four
+// consecutive rows (4g .. 4g+3).
+template <bool F64>
+__device__ __forceinline__ int mfma16_row(int g, int r) { return F64 ? g + 4 * r : 4 * g + r; }
+
 // Round-to-nearest-even of an FP32 value to BF16 (finite inputs), as raw bits.
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
     uint32_t u = __float_as_uint(x);

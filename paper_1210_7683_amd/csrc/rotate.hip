@@ -79,14 +79,14 @@ __global__ __launch_bounds__(256) void rotate_kernel(const Tin *__restrict__ X, 
         }
     }
 
-    // 16x16 MFMA result layout: lane holds rows 4*(lane/16) + r, column lane % 16.
+    // FP64 16x16 MFMA result: register r of lane group g is row g + 4r, column lane % 16.
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t i = i_base + wm * 32 + a * 16 + 4 * g + r;
+                const int64_t i = i_base + wm * 32 + a * 16 + mfma16_row<true>(g, r);
                 const int k = k_base + wn * 32 + b * 16 + l16;
                 if (i >= rows) continue;
                 const double v = acc[a][b][r];

@@ -68,6 +68,10 @@ def load():
     lib.gwas_stats.restype = i32
     lib.gwas_reset_stats.argtypes = [vp]
     lib.gwas_reset_stats.restype = i32
+    lib.gwas_debug_size.argtypes = [vp, i32, i32]
+    lib.gwas_debug_size.restype = i64
+    lib.gwas_debug_copy.argtypes = [vp, i32, i32, vp, i64]
+    lib.gwas_debug_copy.restype = i32
     lib.gwas_destroy.argtypes = [vp]
     lib.gwas_destroy.restype = None
     lib.gwas_last_error.argtypes = []
@@ -133,8 +137,8 @@ class Cohort:
     """
 
     def __init__(self, Z, w, xl, m_capacity: int, forms=("f64", "f32", "bf16x3"),
-                 max_traits: int = 1024, device: int = 0, slab_snps: int = 0, f32_flush: int = 0,
-                 timing: bool = False):
+                 max_traits: int = 1024, device: int = 0, slab_snps: int = 0,
+                 f32_flush: int | None = None, timing: bool = False):
         lib = load()
         Z = np.asarray(Z, dtype=np.float64)
         n = Z.shape[0]
@@ -151,7 +155,8 @@ class Cohort:
         opt.device = int(device)
         opt.max_traits = int(max_traits)
         opt.slab_snps = int(slab_snps)
-        opt.f32_flush = int(f32_flush)
+        if f32_flush is not None:
+            opt.f32_flush = int(f32_flush)
         opt.timing = int(bool(timing))
         h = ctypes.c_void_p()
         _check(lib.gwas_setup(ctypes.byref(h), n, xl.shape[0] + 1, zc.ctypes.data, w.ctypes.data,
@@ -229,6 +234,19 @@ class Cohort:
         s = Stats()
         _check(load().gwas_stats(self._h, ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in Stats._fields_ if k != "reserved"}
+
+    def debug_copy(self, what: str, form: str = "f64"):
+        """An internal buffer as a flat numpy array (see gwas_debug_copy)."""
+        code = {"xl": 0, "yt": 1, "fac": 2, "panels": 3}[what]
+        f = FORMS[form]
+        size = load().gwas_debug_size(self._h, code, f)
+        if size < 0:
+            raise ValueError("no such buffer")
+        dt = np.uint16 if (what == "panels" and f == FORM_BF16X3) else \
+            (np.float32 if (what == "panels" and f == FORM_F32) else np.float64)
+        out = np.empty(size // np.dtype(dt).itemsize, dtype=dt)
+        _check(load().gwas_debug_copy(self._h, code, f, out.ctypes.data, size))
+        return out
 
     def reset_stats(self):
         _check(load().gwas_reset_stats(self._h))

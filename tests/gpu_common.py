@@ -4,12 +4,29 @@ import numpy as np
 import oracle
 from paper_1210_7683_amd import gwas
 
-# Per-problem relative 2-norm error bounds of b against the FP64 oracle.
-TOL = {"f64": 1e-10, "f32": 1e-5, "bf16x3": 2e-3}
+# Error bounds of b against the FP64 oracle, per form: FP64 and FP32 are the
+# stated targets; split BF16 is the measured bound, with margin.
+TOL = {"f64": 1e-10, "f32": 1e-5, "bf16x3": 2e-4}
 
 
 def rel_err(b_hat, b_ref):
+    """Per-problem relative error ||b_hat - b||_2 / ||b||_2."""
     return oracle.relative_error(b_hat, b_ref)
+
+
+def scaled_err(b_hat, b_ref, trait_axis=1):
+    """Per-problem error relative to max(||b||, median ||b|| over the trait's problems).
+
+    When a trait carries no signal at a SNP, b is close to zero and its
+    relative error measures the rounding floor of the sums divided by ||b||;
+    flooring the denominator at the trait's typical ||b|| keeps the measure
+    about the arithmetic, not about how close to zero a particular b falls.
+    """
+    b_hat = np.asarray(b_hat, dtype=np.float64)
+    b_ref = np.asarray(b_ref, dtype=np.float64)
+    nb = np.linalg.norm(b_ref, axis=-1)
+    med = np.median(nb, axis=tuple(a for a in range(nb.ndim) if a != trait_axis), keepdims=True)
+    return np.linalg.norm(b_hat - b_ref, axis=-1) / np.maximum(nb, med)
 
 
 def cohort(phi, xl, xr, forms=("f64", "f32", "bf16x3"), m_capacity=None, **kw):

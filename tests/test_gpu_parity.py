@@ -2,15 +2,20 @@
 
 Every test here runs the kernels on cuda:0 and compares b element by element
 with the oracle (oracle/oracle.c, a dense-Cholesky solve of Eq. (1)) on the
-same seeded inputs, to the per-form bound of the relative error of b_ij:
-FP64 1e-10, FP32 1e-5, split BF16 2e-3 (its measured bound, stated).
+same seeded inputs, to the per-form bound: FP64 1e-10, FP32 1e-5, split BF16
+2e-4 (its measured bound, with margin). On the paper-shaped workloads (p = 4)
+the bound applies to every problem's relative error ||b_hat - b|| / ||b||; on
+the ragged shapes (p from 2 to 20, short n) it applies to the error scaled by
+max(||b||, the trait's median ||b||), since with p = 2 a few problems out of
+thousands have ||b|| near zero and their relative error is the rounding floor
+of the sums divided by ||b|| (reported, not bounded).
 """
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from tests.gpu_common import TOL, cohort, rel_err
+from tests.gpu_common import TOL, cohort, rel_err, scaled_err
 
 pytestmark = pytest.mark.gpu
 
@@ -84,8 +89,11 @@ def test_ragged_shapes_and_p(form, n, p, m, t, torch_cuda):
     b = c.solve(y, h2, form=form).cpu().numpy()
     c.close()
     err = rel_err(b, ref)
-    print("n=%d p=%d m=%d t=%d %s: max %.3e" % (n, p, m, t, form, err.max()))
-    assert err.max() <= TOL[form]
+    sc = scaled_err(b, ref)
+    print("n=%d p=%d m=%d t=%d %s: relative max %.3e, scaled max %.3e" % (n, p, m, t, form,
+                                                                       err.max(), sc.max()))
+    assert sc.max() <= TOL[form]
+    assert np.quantile(err, 0.99) <= TOL[form]
 
 
 @pytest.mark.parametrize("form", FORMS)
@@ -132,7 +140,7 @@ def test_rank_deficient_snps_give_nan_and_are_counted(form, torch_cuda):
     assert np.isfinite(b[ok]).all()
     assert c.stats()["non_spd"] == 2 * 6
     ref = oracle.gls_grid(phi, xl, cols[ok], y, h2)
-    assert rel_err(b[ok], ref).max() <= TOL[form]
+    assert scaled_err(b[ok], ref).max() <= TOL[form]
     c.close()
 
 
@@ -180,10 +188,14 @@ def paper_m1e5(torch_cuda):
 def test_paper_shape_sampled_against_oracle(paper_m1e5, form, torch_cuda):
     d = paper_m1e5
     b = d["c"].solve(d["yd"], d["h2"], form=form)
-    ii, jj = synth.sample_problems(d["w"], 2000, salt=1)
-    keep = np.isin(jj, np.unique(jj)[:6])              # six traits keep the oracle to seconds
-    ii, jj = ii[keep][:120], jj[keep][:120]
-    got = b[ii, jj].cpu().numpy()
+    # six random traits (one O(n^3) factorisation each keeps the oracle to seconds),
+    # 60 random SNPs each, plus the first and last SNP and trait of the grid
+    rng = np.random.default_rng(11)
+    traits = np.concatenate([[0, d["w"].t - 1], rng.choice(np.arange(1, d["w"].t - 1), 4, replace=False)])
+    jj = np.repeat(traits, 62)
+    ii = np.concatenate([np.concatenate([[0, d["w"].m - 1], rng.choice(d["w"].m, 60, replace=False)])
+                         for _ in traits])
+    got = b[torch_cuda.from_numpy(ii).cuda(), torch_cuda.from_numpy(jj).cuda()].cpu().numpy()
     uj, inv = np.unique(jj, return_inverse=True)
     ref = oracle.gls(d["phi"], d["xl"], synth.snp_columns(d["w"], ii), d["y"][uj], d["h2"][uj],
                      trait=inv)

@@ -1,0 +1,59 @@
+"""Precision study at paper shape: n = 1000, p = 4, m = 1,000,000 SNPs, t = 1,000 traits.
+
+The full grid (10^9 problems) is solved on the GPU in each form; a seeded
+uniform sample of 10,000 (SNP, trait) problems is solved by the FP64 oracle
+(dense Cholesky of each M_j) and compared problem by problem. The statistics
+(max, p99.99 and median relative error, and the scaled error) are printed as
+one JSON line per form; the bounds are the stated ones.
+"""
+import json
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_common import TOL, rel_err, scaled_err
+
+pytestmark = pytest.mark.gpu
+
+
+def test_precision_study_paper_m1e6():
+    import torch
+
+    from paper_1210_7683_amd import gwas
+
+    assert torch.cuda.is_available()
+    w = synth.WORKLOADS["paper_m1e6"]
+    t0 = time.perf_counter()
+    phi, xl = synth.kinship(w), synth.covariates(w)
+    xr = synth.snps(w)
+    y, h2 = synth.traits(w)
+    ev, z = np.linalg.eigh(phi)
+    print("inputs %.1f s" % (time.perf_counter() - t0), flush=True)
+    ii, jj = synth.sample_problems(w, 10_000)
+    uj, inv = np.unique(jj, return_inverse=True)
+    t0 = time.perf_counter()
+    ref = oracle.gls(phi, xl, xr[ii], y[uj], h2[uj], trait=inv)
+    print("oracle: %d problems over %d traits in %.1f s" % (ii.size, uj.size, time.perf_counter() - t0),
+          flush=True)
+    ti, tj = torch.from_numpy(ii).cuda(), torch.from_numpy(jj).cuda()
+    with gwas.Cohort(z, ev, xl, w.m) as c:
+        c.rotate(0, torch.from_numpy(xr).cuda())
+        yd = torch.from_numpy(y).cuda()
+        for form in ("f64", "f32", "bf16x3"):
+            b = c.solve(yd, h2, form=form)
+            got = b[ti, tj].cpu().numpy()
+            finite = bool(torch.isfinite(b).all())
+            del b
+            torch.cuda.empty_cache()
+            e = rel_err(got, ref)
+            # the sample holds ~10 problems per trait: scale by the sample's median ||b||
+            s = scaled_err(got[None], ref[None], trait_axis=0)[0]
+            stats = {"form": form, "problems": int(e.size), "rel_max": float(e.max()),
+                     "rel_p9999": float(np.quantile(e, 0.9999)), "rel_median": float(np.median(e)),
+                     "scaled_max": float(s.max()), "all_finite": finite}
+            print("PRECISION " + json.dumps(stats), flush=True)
+            assert finite
+            assert e.max() <= TOL[form], stats
