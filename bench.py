@@ -75,6 +75,9 @@ def main():
     ap.add_argument("--f32-flush", type=int, default=None,
                     help="FP32 form: FP64 fold interval in chunks of 16 samples (library default 2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="one step of the headline form plus a plain 1 GiB device copy (for counter "
+                         "calibration), no timing output; meant to run under rocprofv3")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the GLS grid shards along SNPs with no exchange, "
@@ -98,14 +101,30 @@ def main():
     ev, z = np.linalg.eigh(phi)
     log("inputs drawn and Phi eigendecomposed in %.1f s" % (time.perf_counter() - t0))
 
-    cohort = gwas.Cohort(z, ev, xl, w.m, forms=tuple(forms), timing=True, f32_flush=args.f32_flush)
     xr_d = torch.from_numpy(xr).cuda()
     y_d = torch.from_numpy(y).cuda()
     torch.cuda.synchronize()
     problems = w.m * w.t
     flops_gls = cm.flops_per_gls_contraction(w.n, w.p)
+    if args.profile_pass:
+        form = forms[0]
+        with gwas.Cohort(z, ev, xl, w.m, forms=(form,), f32_flush=args.f32_flush) as cohort:
+            b = torch.empty((w.m, w.t, w.p), dtype=torch.float64 if form == "f64" else torch.float32,
+                            device="cuda")
+            cohort.rotate(0, xr_d)
+            cohort.solve(y_d, h2, form=form, out=b)
+            torch.cuda.synchronize()
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("profile pass done: one %s step and a 1 GiB device copy" % form)
+        return
     results = {}
     for form in forms:
+        # one cohort per form, holding only that form's rotated SNPs, so a step's
+        # rotation writes exactly what the form's solve reads
+        cohort = gwas.Cohort(z, ev, xl, w.m, forms=(form,), timing=True, f32_flush=args.f32_flush)
         dt = torch.float64 if form == "f64" else torch.float32
         b = torch.empty((w.m, w.t, w.p), dtype=dt, device="cuda")
 
@@ -148,8 +167,8 @@ def main():
             "= %.1f%% of %s peak" % (form, ms, fused_ms, rot_ms, results[form]["gls_per_s"],
                                       achieved, 100 * achieved / PEAK_TFLOPS[form], form))
         del b
+        cohort.close()
         torch.cuda.empty_cache()
-    cohort.close()
 
     head = forms[0]
     r = results[head]

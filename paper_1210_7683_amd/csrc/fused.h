@@ -19,10 +19,12 @@
 //   BF16X3: bf16 hi/lo operands, v_mfma_f32_16x16x32_bf16, three products
 //           hi*hi + hi*lo + lo*hi per pair, FP32 accumulation
 //
-// K chunking: each chunk stages 64 bytes of every operand row (8 doubles,
-// 16 floats or 32 bf16). Lane (l16, g) of a wave reads the 16-byte segment g
-// of row l16 of a 16-row fragment; the same segment->k mapping is used for
-// both operands, so every product pairs equal k.
+// K chunking: each chunk stages CB bytes of every operand row in LDS (row
+// stride CB + 16 bytes, so 16-byte reads of 16 consecutive rows fall on
+// distinct banks). Within a 64-byte group, lane (l16, g) of a wave reads the
+// 16-byte segment g of row l16 of a 16-row fragment (2 doubles, 4 floats or 8
+// bf16); the same segment->k mapping is used for both operands, so every
+// product pairs equal k.
 #pragma once
 
 #include <type_traits>
@@ -31,15 +33,33 @@
 
 namespace gw {
 
+// Tile shape of the fused kernel: WM x WN waves, each holding FM x FN 16x16
+// MFMA blocks per contraction; CB bytes of every operand row staged per K
+// chunk (64, 128 or 256); DB = 1 double-buffers the LDS stage (one barrier per
+// chunk, the next chunk's global loads in flight during the MFMAs).
+template <int WM_, int WN_, int FM_, int FN_, int CB_, int DB_>
+struct Tile {
+    static constexpr int WM = WM_, WN = WN_, FM = FM_, FN = FN_, CB = CB_, DB = DB_;
+};
+
+// Per-form tiles, chosen by timing sweeps on the MI355X at n = 1000, p = 4
+// (m = 1e5, t = 1000); larger p uses smaller tiles to bound the registers held
+// by the p+1 accumulator sets.
 template <int FORM, int P, bool FLUSH>
+struct DefaultTile {
+    using F64T = typename std::conditional<(P <= 4), Tile<4, 1, 1, 2, 128, 1>,
+                 typename std::conditional<(P <= 9), Tile<4, 1, 1, 1, 128, 1>, Tile<2, 2, 1, 1, 64, 0>>::type>::type;
+    using F32T = typename std::conditional<(P <= 9), Tile<2, 2, 2, (FLUSH ? 1 : 2), 128, 0>,
+                                           Tile<2, 2, 1, 1, 64, 0>>::type;
+    using BF16T = typename std::conditional<(P <= 4), Tile<2, 2, 4, 2, 64, 0>,
+                  typename std::conditional<(P <= 9), Tile<4, 1, 1, 1, 64, 0>, Tile<2, 1, 1, 1, 64, 0>>::type>::type;
+    using type = typename std::conditional<FORM == GWAS_FORM_F64, F64T,
+                 typename std::conditional<FORM == GWAS_FORM_F32, F32T, BF16T>::type>::type;
+};
+
+template <int FORM, int P, class T>
 struct FusedCfg {
-    // waves along M and N, 16x16 MFMA blocks per wave along M and N
-    static constexpr int WM = (FORM == GWAS_FORM_BF16X3) ? (P <= 4 ? 2 : (P <= 9 ? 4 : 2)) : 2;
-    static constexpr int WN = (FORM == GWAS_FORM_BF16X3) ? (P <= 4 ? 2 : 1) : 2;
-    static constexpr int FM = (FORM == GWAS_FORM_BF16X3) ? (P <= 4 ? 2 : 1) : (P <= 9 ? 2 : 1);
-    static constexpr int FN = (FORM == GWAS_FORM_BF16X3) ? 1
-                            : (FORM == GWAS_FORM_F64)    ? (P <= 4 ? 2 : 1)
-                            : (FLUSH ? (P <= 4 ? 2 : 1) : (P <= 9 ? 2 : 1));
+    static constexpr int WM = T::WM, WN = T::WN, FM = T::FM, FN = T::FN, CB = T::CB, DB = T::DB;
     static constexpr int NT = 64 * WM * WN;
     static constexpr int TM = WM * FM * 16;
     static constexpr int TN = WN * FN * 16;
@@ -47,28 +67,29 @@ struct FusedCfg {
     static constexpr int NA = (FORM == GWAS_FORM_BF16X3) ? 4 : 1;        // SNP-side planes
     static constexpr int NB = (FORM == GWAS_FORM_BF16X3) ? 2 * NQ : NQ;  // trait-side planes
     static constexpr int ESZ = (FORM == GWAS_FORM_F64) ? 8 : (FORM == GWAS_FORM_F32 ? 4 : 2);
-    static constexpr int SEG_A = NA * TM * (kChunkBytes / 16);
-    static constexpr int SEG_B = NB * TN * (kChunkBytes / 16);
+    static constexpr int SPR = CB / 16;          // 16-byte segments per row per chunk
+    static constexpr int RS = CB + 16;           // LDS row stride
+    static constexpr int SEG_A = NA * TM * SPR;
+    static constexpr int SEG_B = NB * TN * SPR;
     static constexpr int LA = (SEG_A + NT - 1) / NT;
     static constexpr int LB = (SEG_B + NT - 1) / NT;
-    static constexpr int LDS = (NA * TM + NB * TN) * kRowStride;
-    static_assert(LDS <= 65536, "LDS tile too large");
+    static constexpr int STAGE = (NA * TM + NB * TN) * RS;
+    static constexpr int LDS = STAGE * (DB ? 2 : 1);
+    static_assert(LDS <= 160 * 1024, "LDS tile too large");
 };
 
 template <typename T>
 __device__ __forceinline__ T load16(const uint8_t *p) { return *(const T *)p; }
 
-template <int FORM, int P, bool FLUSH>
-__global__ __launch_bounds__((FusedCfg<FORM, P, FLUSH>::NT)) void fused_kernel(FusedArgs a) {
-    using C = FusedCfg<FORM, P, FLUSH>;
+template <int FORM, int P, bool FLUSH, class T>
+__global__ __launch_bounds__((FusedCfg<FORM, P, T>::NT)) void fused_kernel(FusedArgs a) {
+    using C = FusedCfg<FORM, P, T>;
     constexpr int NQ = C::NQ, TM = C::TM, TN = C::TN, NT = C::NT;
     constexpr int FM = C::FM, FN = C::FN, WM = C::WM;
-    constexpr int SPR = kChunkBytes / 16;   // 16-byte segments per row per chunk
+    constexpr int SPR = C::SPR, RS = C::RS, CB = C::CB;
     using acc_t = typename std::conditional<FORM == GWAS_FORM_F64, d4, f4>::type;
 
-    __shared__ __attribute__((aligned(16))) uint8_t lds[C::LDS];
-    uint8_t *lA = lds;
-    uint8_t *lB = lds + C::NA * TM * kRowStride;
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
 
     const int ntn = (a.tb + TN - 1) / TN;
     const int64_t tile = blockIdx.x;
@@ -83,7 +104,7 @@ __global__ __launch_bounds__((FusedCfg<FORM, P, FLUSH>::NT)) void fused_kernel(F
     const int l16 = lane & 15, g = lane >> 4;
 
     const int64_t row_bytes = (int64_t)a.n_pad * C::ESZ;
-    const int nchunks = (int)(row_bytes / kChunkBytes);
+    const int nchunks = (int)(row_bytes / CB);
     const uint8_t *A = (const uint8_t *)a.a;
     const uint8_t *B = (const uint8_t *)a.panels;
     const int64_t a_plane = a.a_plane_rows * row_bytes;
@@ -100,8 +121,7 @@ __global__ __launch_bounds__((FusedCfg<FORM, P, FLUSH>::NT)) void fused_kernel(F
                 const int row = rem / SPR, sg = rem % SPR;
                 const int64_t i = m_base + row;
                 if (i < a.mi)
-                    v = load16<uint4>(A + pl * a_plane + (a.i0 + i) * row_bytes +
-                                      (int64_t)c * kChunkBytes + sg * 16);
+                    v = load16<uint4>(A + pl * a_plane + (a.i0 + i) * row_bytes + (int64_t)c * CB + sg * 16);
             }
             ra[u] = v;
         }
@@ -114,20 +134,21 @@ __global__ __launch_bounds__((FusedCfg<FORM, P, FLUSH>::NT)) void fused_kernel(F
                 const int row = rem / SPR, sg = rem % SPR;
                 const int j = n_base + row;
                 if (j < a.tb)
-                    v = load16<uint4>(B + pl * b_plane + (int64_t)j * row_bytes +
-                                      (int64_t)c * kChunkBytes + sg * 16);
+                    v = load16<uint4>(B + pl * b_plane + (int64_t)j * row_bytes + (int64_t)c * CB + sg * 16);
             }
             rb[u] = v;
         }
     };
-    auto sstore = [&]() {
+    auto sstore = [&](uint8_t *stage) {
+        uint8_t *lA = stage;
+        uint8_t *lB = stage + C::NA * TM * RS;
 #pragma unroll
         for (int u = 0; u < C::LA; ++u) {
             const int seg = tid + u * NT;
             if (seg < C::SEG_A) {
                 const int pl = seg / (TM * SPR), rem = seg % (TM * SPR);
                 const int row = rem / SPR, sg = rem % SPR;
-                *(uint4 *)(lA + (pl * TM + row) * kRowStride + sg * 16) = ra[u];
+                *(uint4 *)(lA + (pl * TM + row) * RS + sg * 16) = ra[u];
             }
         }
 #pragma unroll
@@ -136,7 +157,7 @@ __global__ __launch_bounds__((FusedCfg<FORM, P, FLUSH>::NT)) void fused_kernel(F
             if (seg < C::SEG_B) {
                 const int pl = seg / (TN * SPR), rem = seg % (TN * SPR);
                 const int row = rem / SPR, sg = rem % SPR;
-                *(uint4 *)(lB + (pl * TN + row) * kRowStride + sg * 16) = rb[u];
+                *(uint4 *)(lB + (pl * TN + row) * RS + sg * 16) = rb[u];
             }
         }
     };
@@ -152,27 +173,40 @@ __global__ __launch_bounds__((FusedCfg<FORM, P, FLUSH>::NT)) void fused_kernel(F
                 acc[q][x][y] = acc_t{0, 0, 0, 0};
                 if constexpr (FLUSH) acc64[q][x][y] = d4{0, 0, 0, 0};
             }
+    auto fold = [&]() {
+        if constexpr (FLUSH) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+#pragma unroll
+                for (int x = 0; x < FM; ++x)
+#pragma unroll
+                    for (int y = 0; y < FN; ++y) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc64[q][x][y][r] += (double)acc[q][x][y][r];
+                        acc[q][x][y] = acc_t{0, 0, 0, 0};
+                    }
+        }
+    };
+    int fold_count = 0;
 
     const int arow0 = wm * FM * 16 + l16;
     const int brow0 = wn * FN * 16 + l16;
 
-    gload(0);
-    for (int c = 0; c < nchunks; ++c) {
-        __syncthreads();
-        sstore();
-        __syncthreads();
-        if (c + 1 < nchunks) gload(c + 1);
-
+    // MFMAs of one 64-byte group of a staged chunk: lane group g reads the
+    // 16-byte segment sg of its rows (the same segment of A and B rows).
+    auto compute = [&](const uint8_t *stage, int sg) {
+        const uint8_t *lA = stage;
+        const uint8_t *lB = stage + C::NA * TM * RS;
+        const int off = sg * 16;
         if constexpr (FORM == GWAS_FORM_F64) {
             double2 av[FM];
 #pragma unroll
-            for (int x = 0; x < FM; ++x) av[x] = load16<double2>(lA + (arow0 + x * 16) * kRowStride + g * 16);
+            for (int x = 0; x < FM; ++x) av[x] = load16<double2>(lA + (arow0 + x * 16) * RS + off);
 #pragma unroll
             for (int y = 0; y < FN; ++y) {
                 double2 bv[NQ];
 #pragma unroll
-                for (int q = 0; q < NQ; ++q)
-                    bv[q] = load16<double2>(lB + (q * TN + brow0 + y * 16) * kRowStride + g * 16);
+                for (int q = 0; q < NQ; ++q) bv[q] = load16<double2>(lB + (q * TN + brow0 + y * 16) * RS + off);
 #pragma unroll
                 for (int x = 0; x < FM; ++x) {
                     const double x0 = av[x].x, x1 = av[x].y;
@@ -188,13 +222,12 @@ __global__ __launch_bounds__((FusedCfg<FORM, P, FLUSH>::NT)) void fused_kernel(F
         } else if constexpr (FORM == GWAS_FORM_F32) {
             float4 av[FM];
 #pragma unroll
-            for (int x = 0; x < FM; ++x) av[x] = load16<float4>(lA + (arow0 + x * 16) * kRowStride + g * 16);
+            for (int x = 0; x < FM; ++x) av[x] = load16<float4>(lA + (arow0 + x * 16) * RS + off);
 #pragma unroll
             for (int y = 0; y < FN; ++y) {
                 float4 bv[NQ];
 #pragma unroll
-                for (int q = 0; q < NQ; ++q)
-                    bv[q] = load16<float4>(lB + (q * TN + brow0 + y * 16) * kRowStride + g * 16);
+                for (int q = 0; q < NQ; ++q) bv[q] = load16<float4>(lB + (q * TN + brow0 + y * 16) * RS + off);
 #pragma unroll
                 for (int x = 0; x < FM; ++x) {
                     const float xs[4] = {av[x].x, av[x].y, av[x].z, av[x].w};
@@ -212,17 +245,9 @@ __global__ __launch_bounds__((FusedCfg<FORM, P, FLUSH>::NT)) void fused_kernel(F
                 }
             }
             if constexpr (FLUSH) {
-                if (((c + 1) % a.f32_flush) == 0 || c + 1 == nchunks) {
-#pragma unroll
-                    for (int q = 0; q < NQ; ++q)
-#pragma unroll
-                        for (int x = 0; x < FM; ++x)
-#pragma unroll
-                            for (int y = 0; y < FN; ++y) {
-#pragma unroll
-                                for (int r = 0; r < 4; ++r) acc64[q][x][y][r] += (double)acc[q][x][y][r];
-                                acc[q][x][y] = acc_t{0, 0, 0, 0};
-                            }
+                if (++fold_count == a.f32_flush) {
+                    fold();
+                    fold_count = 0;
                 }
             }
         } else {
@@ -230,15 +255,14 @@ __global__ __launch_bounds__((FusedCfg<FORM, P, FLUSH>::NT)) void fused_kernel(F
 #pragma unroll
             for (int pl = 0; pl < 4; ++pl)
 #pragma unroll
-                for (int x = 0; x < FM; ++x)
-                    av[pl][x] = load16<bf16x8>(lA + (pl * TM + arow0 + x * 16) * kRowStride + g * 16);
+                for (int x = 0; x < FM; ++x) av[pl][x] = load16<bf16x8>(lA + (pl * TM + arow0 + x * 16) * RS + off);
 #pragma unroll
             for (int y = 0; y < FN; ++y) {
                 bf16x8 bh[NQ], bl[NQ];
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
-                    bh[q] = load16<bf16x8>(lB + ((2 * q) * TN + brow0 + y * 16) * kRowStride + g * 16);
-                    bl[q] = load16<bf16x8>(lB + ((2 * q + 1) * TN + brow0 + y * 16) * kRowStride + g * 16);
+                    bh[q] = load16<bf16x8>(lB + ((2 * q) * TN + brow0 + y * 16) * RS + off);
+                    bl[q] = load16<bf16x8>(lB + ((2 * q + 1) * TN + brow0 + y * 16) * RS + off);
                 }
 #pragma unroll
                 for (int x = 0; x < FM; ++x) {
@@ -255,7 +279,32 @@ __global__ __launch_bounds__((FusedCfg<FORM, P, FLUSH>::NT)) void fused_kernel(F
                 }
             }
         }
+    };
+
+    if constexpr (C::DB) {
+        gload(0);
+        sstore(lds);
+        __syncthreads();
+        for (int c = 0; c < nchunks; ++c) {
+            uint8_t *cur = lds + (c & 1) * C::STAGE;
+            if (c + 1 < nchunks) gload(c + 1);
+#pragma unroll
+            for (int h = 0; h < CB / 64; ++h) compute(cur, 4 * h + g);
+            if (c + 1 < nchunks) sstore(lds + ((c + 1) & 1) * C::STAGE);
+            __syncthreads();
+        }
+    } else {
+        gload(0);
+        for (int c = 0; c < nchunks; ++c) {
+            __syncthreads();
+            sstore(lds);
+            __syncthreads();
+            if (c + 1 < nchunks) gload(c + 1);
+#pragma unroll
+            for (int h = 0; h < CB / 64; ++h) compute(lds, 4 * h + g);
+        }
     }
+    if constexpr (FLUSH) fold();
 
     // FP64 epilogue: Gram assembly and the p x p solve, lane-local.
     constexpr int Q = P - 1;
@@ -268,9 +317,18 @@ __global__ __launch_bounds__((FusedCfg<FORM, P, FLUSH>::NT)) void fused_kernel(F
             const int j = n_base + wn * FN * 16 + y * 16 + l16;
             if (j >= a.tb) continue;
             const double *F = a.fac + (int64_t)j * a.fac_stride;
-            double Lf[NTL], z[Q];
+            // small p: the trait's factor is cached in registers; large p reads it
+            // from memory (L1/L2-resident) to keep the epilogue free of spills
+            constexpr bool CACHE = NTL <= 36;
+            double Lc[CACHE ? NTL : 1], z[Q];
+            if constexpr (CACHE) {
 #pragma unroll
-            for (int u = 0; u < NTL; ++u) Lf[u] = F[u];
+                for (int u = 0; u < NTL; ++u) Lc[u] = F[u];
+            }
+            auto Lf = [&](int u) -> double {
+                if constexpr (CACHE) return Lc[u];
+                else return F[u];
+            };
 #pragma unroll
             for (int u = 0; u < Q; ++u) z[u] = F[NTL + u];
 #pragma unroll
@@ -289,7 +347,7 @@ __global__ __launch_bounds__((FusedCfg<FORM, P, FLUSH>::NT)) void fused_kernel(F
                 for (int aa = 0; aa < Q; ++aa) {
                     double v = 0.0;
 #pragma unroll
-                    for (int bb = 0; bb <= aa; ++bb) v += Lf[aa * (aa + 1) / 2 + bb] * cq[1 + bb];
+                    for (int bb = 0; bb <= aa; ++bb) v += Lf(aa * (aa + 1) / 2 + bb) * cq[1 + bb];
                     u[aa] = v;
                     s -= v * v;
                 }
@@ -305,7 +363,7 @@ __global__ __launch_bounds__((FusedCfg<FORM, P, FLUSH>::NT)) void fused_kernel(F
                 for (int bb = 0; bb < Q; ++bb) {
                     double v = 0.0;
 #pragma unroll
-                    for (int aa = bb; aa < Q; ++aa) v += Lf[aa * (aa + 1) / 2 + bb] * u[aa];
+                    for (int aa = bb; aa < Q; ++aa) v += Lf(aa * (aa + 1) / 2 + bb) * u[aa];
                     out[bb] = v;
                 }
                 out[Q] = beta;
@@ -325,12 +383,21 @@ __global__ __launch_bounds__((FusedCfg<FORM, P, FLUSH>::NT)) void fused_kernel(F
     if (bad) atomicAdd(a.non_spd, (unsigned long long)bad);
 }
 
-template <int FORM, int P, bool FLUSH>
+template <int FORM, int P, bool FLUSH, class T = typename DefaultTile<FORM, P, FLUSH>::type>
 hipError_t launch_fused_t(const FusedArgs &a, hipStream_t s) {
-    using C = FusedCfg<FORM, P, FLUSH>;
+    using C = FusedCfg<FORM, P, T>;
     const int64_t tiles = ((a.mi + C::TM - 1) / C::TM) * ((a.tb + C::TN - 1) / C::TN);
     if (tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL((fused_kernel<FORM, P, FLUSH>), dim3((unsigned)tiles), dim3(C::NT), 0, s, a);
+    if (C::LDS > 65536) {
+        static bool attr_set = false;   // per instantiation
+        if (!attr_set) {
+            hipError_t e = hipFuncSetAttribute((const void *)fused_kernel<FORM, P, FLUSH, T>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS);
+            if (e != hipSuccess) return e;
+            attr_set = true;
+        }
+    }
+    hipLaunchKernelGGL((fused_kernel<FORM, P, FLUSH, T>), dim3((unsigned)tiles), dim3(C::NT), C::LDS, s, a);
     return hipGetLastError();
 }
 

@@ -9,13 +9,9 @@
 namespace gw {
 
 // Sample axis padding: rotated rows are stored with n_pad = round_up(n, 64)
-// values (zeros beyond n), so every K loop runs over whole 64-byte chunks.
+// values (zeros beyond n), so every K loop runs over whole chunks of up to
+// 128 bytes (FP16/BF16), 256 bytes (FP32) or 512 bytes (FP64) per row.
 constexpr int kPadN = 64;
-// Bytes of one row that a K chunk of the fused kernel stages in LDS, and the
-// LDS row stride (16 bytes of padding keep 16-byte reads of 16 consecutive
-// rows on distinct banks).
-constexpr int kChunkBytes = 64;
-constexpr int kRowStride = kChunkBytes + 16;
 
 // Relative floor of the Schur pivot of the SNP column, per form: a problem
 // whose S_BR - |L^{-1} S_BL|^2 does not exceed this fraction of S_BR is

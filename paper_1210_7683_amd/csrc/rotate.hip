@@ -1,6 +1,8 @@
-// Rotation by Z^T (the preloop GEMMs of Algorithm 5): out = X Z, i.e. every
-// input column x (n samples) becomes x' = Z^T x, computed as an FP64 MFMA GEMM
-// (v_mfma_f64_16x16x4) with both operands contiguous along the samples.
+// Rotation by Z^T (the preloop GEMMs of Algorithm 5, bundled over columns as
+// Section 3.2 describes): every input column x (n samples) becomes x' = Z^T x.
+// As a GEMM, out[i][k] = sum_r X[i][r] Z[k][r] (rows of Z are eigenvectors):
+// both operands are contiguous along the samples r, computed in FP64 MFMA
+// (v_mfma_f64_16x16x4f64) over LDS-staged K chunks.
 //
 // The rotated rows are written in every resident form at once: FP64, rounded
 // to FP32, and split to BF16 hi/lo together with the split of the square x'^2
@@ -10,84 +12,109 @@
 namespace gw {
 namespace {
 
-constexpr int RT_M = 64;      // input columns (SNPs / traits) per workgroup
-constexpr int RT_N = 64;      // rotated sample indices per workgroup
-constexpr int RT_K = 16;      // samples per K chunk
-constexpr int RT_LD = RT_K + 2;  // LDS row stride in doubles (16 bytes of padding)
+// TM input columns x TN rotated indices per workgroup of WM x WN waves; KC
+// samples (doubles) staged per K chunk.
+template <int TM_, int TN_, int KC_, int WM_, int WN_>
+struct RotTile {
+    static constexpr int TM = TM_, TN = TN_, KC = KC_, WM = WM_, WN = WN_;
+    static constexpr int NT = 64 * WM * WN;
+    static constexpr int FM = TM / WM / 16, FN = TN / WN / 16;
+    static constexpr int LD = KC + 2;   // LDS row stride in doubles (16 bytes of padding)
+    static constexpr int EA = TM * KC / NT;   // A elements loaded per thread per chunk
+    static constexpr int EB = TN * KC / NT;   // B elements loaded per thread per chunk
+    static_assert(FM >= 1 && FN >= 1 && EA >= 1 && EB >= 2 && KC % 8 == 0, "bad rotation tile");
+};
 
-template <typename T>
-__device__ __forceinline__ double to_f64(T v) { return (double)v; }
+using DefaultRot = RotTile<64, 64, 32, 2, 2>;   // fastest of a tile sweep on MI355X (n = 1000)
 
-template <typename Tin>
-__global__ __launch_bounds__(256) void rotate_kernel(const Tin *__restrict__ X, int64_t rows, int n,
-                                                     int64_t ldx, const double *__restrict__ Zr,
-                                                     int n_pad, RotOut out) {
-    __shared__ double la[RT_M * RT_LD];
-    __shared__ double lb[RT_N * RT_LD];
-    const int ntn = n_pad / RT_N;
+template <typename Tin, class R>
+__global__ __launch_bounds__(R::NT) void rotate_kernel(const Tin *__restrict__ X, int64_t rows, int n,
+                                                       int64_t ldx, const double *__restrict__ Zr,
+                                                       int n_pad, RotOut out) {
+    constexpr int TM = R::TM, TN = R::TN, KC = R::KC, LD = R::LD, FM = R::FM, FN = R::FN;
+    __shared__ __attribute__((aligned(16))) double la[TM * LD];
+    __shared__ __attribute__((aligned(16))) double lb[TN * LD];
+    const int ntn = n_pad / TN;
     const int64_t tile = blockIdx.x;
     const int tn = (int)(tile % ntn);
     const int64_t tm = tile / ntn;
-    const int64_t i_base = tm * RT_M;
-    const int k_base = tn * RT_N;
+    const int64_t i_base = tm * TM;
+    const int k_base = tn * TN;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int wm = wave & 1, wn = wave >> 1;
+    const int wm = wave % R::WM, wn = wave / R::WM;
     const int l16 = lane & 15, g = lane >> 4;
 
-    // loader coordinates: 64 rows x 16 values, 4 consecutive values per thread
-    const int lrow = tid >> 2, lcol = (tid & 3) * 4;
-    const int64_t gi = i_base + lrow;
+    // loaders: thread covers EA consecutive samples of one input row and EB of one Z row
+    constexpr int APR = KC / R::EA;   // threads per A row
+    constexpr int BPR = KC / R::EB;
+    const int arow = tid / APR, acol = (tid % APR) * R::EA;
+    const int brow = tid / BPR, bcol = (tid % BPR) * R::EB;
+    const int64_t gi = i_base + arow;
     const Tin *xrow = X + gi * ldx;
-    const double *zrow = Zr + (int64_t)(k_base + lrow) * n_pad;
+    const double *zrow = Zr + (int64_t)(k_base + brow) * n_pad;
 
-    d4 acc[2][2];
+    d4 acc[FM][FN];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < FM; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-    const int kend = (n + RT_K - 1) / RT_K * RT_K;   // <= n_pad
-    for (int k0 = 0; k0 < kend; k0 += RT_K) {
-        double va[4], vb[4];
+    double va[R::EA], vb[R::EB];
+    auto gload = [&](int k0) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int r = k0 + lcol + e;
-            va[e] = (gi < rows && r < n) ? to_f64(xrow[r]) : 0.0;
-            vb[e] = zrow[r];   // Z rows are n_pad long and zero beyond n
+        for (int e = 0; e < R::EA; ++e) {
+            const int r = k0 + acol + e;
+            va[e] = (gi < rows && r < n) ? (double)xrow[r] : 0.0;
         }
+#pragma unroll
+        for (int e = 0; e < R::EB; e += 2) {
+            const double2 z2 = *(const double2 *)(zrow + k0 + bcol + e);   // Z rows are n_pad long, zero beyond n
+            vb[e] = z2.x;
+            vb[e + 1] = z2.y;
+        }
+    };
+
+    const int kend = (n + KC - 1) / KC * KC;   // <= n_pad (n_pad is a multiple of 64)
+    gload(0);
+    for (int k0 = 0; k0 < kend; k0 += KC) {
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            la[lrow * RT_LD + lcol + e] = va[e];
-            lb[lrow * RT_LD + lcol + e] = vb[e];
-        }
+        for (int e = 0; e < R::EA; ++e) la[arow * LD + acol + e] = va[e];
+#pragma unroll
+        for (int e = 0; e < R::EB; e += 2) *(double2 *)(lb + brow * LD + bcol + e) = double2{vb[e], vb[e + 1]};
         __syncthreads();
+        if (k0 + KC < kend) gload(k0 + KC);
 #pragma unroll
-        for (int s = 0; s < RT_K / 4; ++s) {
-            double fa[2], fb[2];
+        for (int h = 0; h < KC / 8; ++h) {
+            // lane group g reads samples 8h + 2g, 8h + 2g + 1 of its rows (same for A and B)
+            double2 fa[FM], fb[FN];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) fa[a] = la[(wm * 32 + a * 16 + l16) * RT_LD + s * 4 + g];
+            for (int a = 0; a < FM; ++a)
+                fa[a] = *(const double2 *)(la + (wm * FM * 16 + a * 16 + l16) * LD + 8 * h + 2 * g);
 #pragma unroll
-            for (int b = 0; b < 2; ++b) fb[b] = lb[(wn * 32 + b * 16 + l16) * RT_LD + s * 4 + g];
+            for (int b = 0; b < FN; ++b)
+                fb[b] = *(const double2 *)(lb + (wn * FN * 16 + b * 16 + l16) * LD + 8 * h + 2 * g);
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < FM; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+                for (int b = 0; b < FN; ++b) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a].x, fb[b].x, acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a].y, fb[b].y, acc[a][b], 0, 0, 0);
+                }
         }
     }
 
     // FP64 16x16 MFMA result: register r of lane group g is row g + 4r, column lane % 16.
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < FM; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < FN; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t i = i_base + wm * 32 + a * 16 + mfma16_row<true>(g, r);
-                const int k = k_base + wn * 32 + b * 16 + l16;
+                const int64_t i = i_base + wm * FM * 16 + a * 16 + mfma16_row<true>(g, r);
+                const int k = k_base + wn * FN * 16 + b * 16 + l16;
                 if (i >= rows) continue;
                 const double v = acc[a][b][r];
                 const int64_t o = (out.row0 + i) * out.ld + k;
@@ -108,28 +135,35 @@ __global__ __launch_bounds__(256) void rotate_kernel(const Tin *__restrict__ X, 
 
 }  // namespace
 
-hipError_t launch_rotate(const void *X, int dtype, int64_t rows, int n, int64_t ldx,
-                         const double *Zrows, int n_pad, const RotOut &out, hipStream_t s) {
+template <class R>
+hipError_t launch_rotate_t(const void *X, int dtype, int64_t rows, int n, int64_t ldx, const double *Zrows,
+                           int n_pad, const RotOut &out, hipStream_t s) {
     if (rows <= 0) return hipSuccess;
-    const int64_t tiles = ((rows + RT_M - 1) / RT_M) * (n_pad / RT_N);
-    dim3 grid((unsigned)tiles), block(256);
+    if (n_pad % R::TN) return hipErrorInvalidValue;
+    const int64_t tiles = ((rows + R::TM - 1) / R::TM) * (n_pad / R::TN);
+    dim3 grid((unsigned)tiles), block(R::NT);
     switch (dtype) {
     case GWAS_DT_F64:
-        hipLaunchKernelGGL(rotate_kernel<double>, grid, block, 0, s, (const double *)X, rows, n, ldx,
-                           Zrows, n_pad, out);
+        hipLaunchKernelGGL((rotate_kernel<double, R>), grid, block, 0, s, (const double *)X, rows, n, ldx, Zrows,
+                           n_pad, out);
         break;
     case GWAS_DT_F32:
-        hipLaunchKernelGGL(rotate_kernel<float>, grid, block, 0, s, (const float *)X, rows, n, ldx,
-                           Zrows, n_pad, out);
+        hipLaunchKernelGGL((rotate_kernel<float, R>), grid, block, 0, s, (const float *)X, rows, n, ldx, Zrows,
+                           n_pad, out);
         break;
     case GWAS_DT_U8:
-        hipLaunchKernelGGL(rotate_kernel<uint8_t>, grid, block, 0, s, (const uint8_t *)X, rows, n,
-                           ldx, Zrows, n_pad, out);
+        hipLaunchKernelGGL((rotate_kernel<uint8_t, R>), grid, block, 0, s, (const uint8_t *)X, rows, n, ldx,
+                           Zrows, n_pad, out);
         break;
     default:
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_rotate(const void *X, int dtype, int64_t rows, int n, int64_t ldx, const double *Zrows,
+                         int n_pad, const RotOut &out, hipStream_t s) {
+    return launch_rotate_t<DefaultRot>(X, dtype, rows, n, ldx, Zrows, n_pad, out, s);
 }
 
 }  // namespace gw
