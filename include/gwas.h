@@ -68,12 +68,14 @@ typedef struct gwas_options {
                             0 means all three                                         */
     int32_t device;      /* HIP device ordinal; -1: the current device                 */
     int32_t max_traits;  /* traits handled per internal trait sub-block; 0: 1024       */
-    int32_t slab_snps;   /* SNPs per D2H slab when b is host memory; 0: auto           */
+    int32_t slab_snps;   /* SNPs per D2H slab when b goes to the host; 0: 16384        */
     int32_t f32_flush;   /* FP32 form: fold the FP32 accumulators into FP64 every
                             this many K chunks of 16 samples (0: never; default 2)    */
     int32_t timing;      /* nonzero: time every fused and rotation launch with HIP
                             events on its stream (read back by gwas_stats)           */
-    int32_t reserved[8];
+    int32_t ring_slots;  /* gwas_solve_stream: pinned host slots of the b ring; 0: 4  */
+    int32_t host_threads;/* gwas_solve_stream: threads per slab checksum; 0: 8        */
+    int32_t reserved[6];
 } gwas_options;
 
 typedef struct gwas_stats_t {
@@ -148,6 +150,42 @@ gwas_status gwas_rotate(gwas_ctx *ctx, int64_t m0, int64_t mb, const void *X_R, 
 gwas_status gwas_solve(gwas_ctx *ctx, int64_t i0, int64_t mi, int32_t tb, const double *Y,
                        int32_t y_on_device, const double *h2, int32_t form, void *b,
                        int32_t b_on_device, void *stream);
+
+/*
+ * Streamed solve (the b sink of the paper's double-buffering scheme, Section 4,
+ * applied to the device->host link): the grid of SNPs [i0, i0 + mi) x the tb
+ * traits of Y is solved as in gwas_solve, in slabs of gwas_options.slab_snps
+ * SNPs per trait sub-block. Each slab's b is computed into one of two device
+ * buffers while the previous one is copied, on a second stream, into a slot
+ * of a library-owned ring of pinned host memory (gwas_options.ring_slots
+ * slots). The calling thread then waits for the copy, computes the slab's
+ * checksum and, when fn is not NULL, calls fn(user, slab); the slot is reused
+ * once fn returns, so a slow consumer throttles the producer. The call returns
+ * when every slab has been consumed (synchronous).
+ *   checksums   nullable; receives the slab checksums in issue order (up to
+ *               max_checksums of them); *n_slabs receives the slab count
+ * The checksum of a slab is the sum over its 32-bit words w_k (k from 0, in
+ * memory order) of (k + 1) * w_k, modulo 2^64.
+ * Errors: as gwas_solve; GWAS_ENOMEM if the pinned ring cannot be allocated.
+ */
+typedef struct gwas_slab {
+    int64_t index;      /* slab number in issue order                              */
+    int64_t i0, count;  /* SNP range of the slab                                   */
+    int32_t j0, tb;     /* trait range (within the call's traits)                   */
+    int32_t p, form;
+    const void *b;      /* pinned host memory: count x tb x p, p fastest            */
+    int64_t bytes;
+    uint64_t checksum;
+} gwas_slab;
+typedef void (*gwas_slab_fn)(void *user, const gwas_slab *slab);
+
+gwas_status gwas_solve_stream(gwas_ctx *ctx, int64_t i0, int64_t mi, int32_t tb, const double *Y,
+                              int32_t y_on_device, const double *h2, int32_t form, gwas_slab_fn fn,
+                              void *user, uint64_t *checksums, int64_t max_checksums, int64_t *n_slabs,
+                              void *stream);
+
+/* The checksum used by gwas_solve_stream, over bytes (a multiple of 4) at p. */
+uint64_t gwas_checksum(const void *p, int64_t bytes);
 
 /*
  * Copy rotated SNP columns [i0, i0 + mi) out of the resident store, n values

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "gwas_internal.h"
@@ -71,6 +72,12 @@ struct gwas_ctx {
     hipEvent_t ev_done[2] = {nullptr, nullptr};   // slab computed
     hipEvent_t ev_free[2] = {nullptr, nullptr};   // slab copied out
     hipEvent_t ev_side = nullptr;
+
+    // streamed sink: pinned host ring
+    int ring_slots = 4, host_threads = 8;
+    std::vector<void *> ring;
+    size_t ring_bytes = 0;
+    std::vector<hipEvent_t> ring_ev;
 
     int64_t snps_rotated = 0, problems = 0, bytes_h2d = 0, bytes_d2h = 0, resident = 0;
 
@@ -147,6 +154,10 @@ void release(gwas_ctx *c) {
         if (c->ev_free[i]) hipEventDestroy(c->ev_free[i]);
     }
     if (c->ev_side) hipEventDestroy(c->ev_side);
+    for (void *p : c->ring)
+        if (p) hipHostFree(p);
+    for (hipEvent_t e : c->ring_ev)
+        if (e) hipEventDestroy(e);
     if (c->side) hipStreamDestroy(c->side);
     delete c;
 }
@@ -197,7 +208,8 @@ gwas_status gwas_setup(gwas_ctx **out, int32_t n, int32_t p, const double *Z, co
     if (p < 2 || p > 20) return fail(GWAS_EINVAL, "p = %d outside [2, 20]", p);
     if (!Z || !w || !X_L || !opt) return fail(GWAS_EINVAL, "NULL input pointer");
     if (opt->m_capacity <= 0) return fail(GWAS_EINVAL, "m_capacity must be positive");
-    if (opt->max_traits < 0 || opt->slab_snps < 0 || opt->f32_flush < 0)
+    if (opt->max_traits < 0 || opt->slab_snps < 0 || opt->f32_flush < 0 || opt->ring_slots < 0 ||
+        opt->host_threads < 0 || opt->ring_slots > 64 || opt->host_threads > 256)
         return fail(GWAS_EINVAL, "negative option");
     const uint32_t forms = opt->forms ? opt->forms : 7u;
     if (forms & ~7u) return fail(GWAS_EINVAL, "unknown form bits 0x%x", forms);
@@ -220,6 +232,8 @@ gwas_status gwas_setup(gwas_ctx **out, int32_t n, int32_t p, const double *Z, co
     c->tcap = opt->max_traits ? opt->max_traits : 1024;
     c->f32_flush = opt->f32_flush;
     c->timing = opt->timing != 0;
+    c->ring_slots = opt->ring_slots > 0 ? opt->ring_slots : 4;
+    c->host_threads = opt->host_threads > 0 ? opt->host_threads : 8;
     c->w_min = *std::min_element(w, w + n);
 
     gwas_status st;
@@ -268,7 +282,7 @@ gwas_status gwas_setup(gwas_ctx **out, int32_t n, int32_t p, const double *Z, co
     }
 
     // D2H streaming: two staging buffers for b slabs, a side stream, events
-    c->slab = opt->slab_snps ? opt->slab_snps : (int)std::min<int64_t>(c->m_rows, 65536);
+    c->slab = opt->slab_snps ? opt->slab_snps : (int)std::min<int64_t>(c->m_rows, 16384);
     c->bstage_bytes = (size_t)c->slab * c->tcap * p * sizeof(double);
     if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
         release(c); return fail(GWAS_EHIP, "stream creation failed");
@@ -326,10 +340,12 @@ gwas_status gwas_rotate(gwas_ctx *c, int64_t m0, int64_t mb, const void *X, int3
     return GWAS_OK;
 }
 
-gwas_status gwas_solve(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, const double *Y,
-                       int32_t y_on_device, const double *h2, int32_t form, void *b,
-                       int32_t b_on_device, void *stream) {
-    g_err.clear();
+}  // extern "C"
+
+namespace {
+
+gwas_status check_solve(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, const double *Y, int32_t y_on_device,
+                        const double *h2, int32_t form) {
     if (!c) return fail(GWAS_EINVAL, "ctx is NULL");
     if (form < 0 || form > 2) return fail(GWAS_EINVAL, "unknown form %d", form);
     if (!(c->forms & GWAS_FORM_BIT(form))) return fail(GWAS_EINVAL, "form %d is not resident", form);
@@ -337,75 +353,134 @@ gwas_status gwas_solve(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, const do
         return fail(GWAS_EINVAL, "SNP range [%lld, %lld) outside capacity %lld", (long long)i0,
                     (long long)(i0 + mi), (long long)c->m_cap);
     if (tb < 1) return fail(GWAS_EINVAL, "tb = %d must be >= 1", tb);
-    if (!Y || !h2 || (mi > 0 && !b)) return fail(GWAS_EINVAL, "NULL pointer");
+    if (!Y || !h2) return fail(GWAS_EINVAL, "NULL pointer");
     for (int j = 0; j < tb; ++j) {
         const double h = h2[j];
         const bool in_range = (h >= 0.0 && h < 1.0) || (h == 1.0 && c->w_min > 0.0);
         if (!isfinite(h) || !in_range || !(h * c->w_min + (1.0 - h) > 0.0))
             return fail(GWAS_EINVAL, "h2[%d] = %g gives a covariance that is not SPD", j, h);
     }
-    if (!y_on_device && !all_finite(Y, (size_t)tb * c->n))
-        return fail(GWAS_EINVAL, "non-finite value in Y");
+    if (!y_on_device && !all_finite(Y, (size_t)tb * c->n)) return fail(GWAS_EINVAL, "non-finite value in Y");
+    return GWAS_OK;
+}
+
+// Trait sub-block [j0, j0 + jb): stage, rotate y' = Z^T y (FP64), and run the
+// per-trait prologue into the context's panels and factors.
+gwas_status prep_traits(gwas_ctx *c, int j0, int jb, const double *Y, int32_t y_on_device, const double *h2,
+                        int32_t form, hipStream_t s) {
+    const double *ysrc = Y + (size_t)j0 * c->n;
+    if (!y_on_device) {
+        HIP_TRY(hipMemcpyAsync(c->y_in, ysrc, sizeof(double) * (size_t)jb * c->n, hipMemcpyHostToDevice, s));
+        c->bytes_h2d += (int64_t)sizeof(double) * jb * c->n;
+        ysrc = c->y_in;
+    }
+    HIP_TRY(hipMemcpyAsync(c->h2, h2 + j0, sizeof(double) * jb, hipMemcpyHostToDevice, s));
+    RotOut ro{c->yt, nullptr, nullptr, 0, 0, c->n_pad};
+    HIP_TRY(launch_rotate(ysrc, GWAS_DT_F64, jb, c->n, c->n, c->Z, c->n_pad, ro, s));
+    PrepArgs pa{c->yt, c->h2, c->w, c->xlt, c->panels[form], c->fac, jb, c->n, c->n_pad, c->p, c->tcap,
+                fac_stride(c->p), form};
+    HIP_TRY(launch_prep(pa, s));
+    return GWAS_OK;
+}
+
+FusedArgs fused_args(gwas_ctx *c, int jb, int32_t form) {
+    FusedArgs fa{};
+    fa.a = form == GWAS_FORM_F64 ? (const void *)c->xr64
+         : form == GWAS_FORM_F32 ? (const void *)c->xr32 : (const void *)c->xrbf;
+    fa.a_plane_rows = c->m_rows;
+    fa.panels = c->panels[form];
+    fa.tcap = c->tcap;
+    fa.fac = c->fac;
+    fa.fac_stride = fac_stride(c->p);
+    fa.tb = jb;
+    fa.n_pad = c->n_pad;
+    fa.p = c->p;
+    fa.rank_rtol = kRankRtol[form];
+    fa.non_spd = c->counters;
+    fa.f32_flush = form == GWAS_FORM_F32 ? c->f32_flush : 0;
+    return fa;
+}
+
+gwas_status launch_fused_timed(gwas_ctx *c, int32_t form, const FusedArgs &fa, hipStream_t s) {
+    std::pair<hipEvent_t, hipEvent_t> ev{};
+    HIP_TRY(timed_begin(c, s, ev));
+    HIP_TRY(launch_fused(form, fa, s));
+    HIP_TRY(timed_end(c, s, ev, c->t_fused));
+    return GWAS_OK;
+}
+
+gwas_status ensure_bstage(gwas_ctx *c) {
+    if (c->bstage[0]) return GWAS_OK;
+    for (int u = 0; u < 2; ++u) {
+        hipError_t e = hipMalloc(&c->bstage[u], c->bstage_bytes);
+        if (e != hipSuccess)
+            return fail(GWAS_ENOMEM, "b staging (%zu bytes): %s", c->bstage_bytes, hipGetErrorString(e));
+        c->resident += (int64_t)c->bstage_bytes;
+    }
+    return GWAS_OK;
+}
+
+uint64_t checksum_range(const uint32_t *w, int64_t k0, int64_t k1) {
+    uint64_t s = 0;
+    for (int64_t k = k0; k < k1; ++k) s += (uint64_t)(k + 1) * (uint64_t)w[k];
+    return s;
+}
+
+uint64_t checksum_parallel(const void *p, int64_t bytes, int threads) {
+    const uint32_t *w = (const uint32_t *)p;
+    const int64_t words = bytes / 4;
+    if (threads <= 1 || words < (1 << 20)) return checksum_range(w, 0, words);
+    std::vector<uint64_t> part(threads, 0);
+    std::vector<std::thread> pool;
+    const int64_t per = (words + threads - 1) / threads;
+    for (int t = 0; t < threads; ++t)
+        pool.emplace_back([&, t] {
+            const int64_t k0 = std::min(words, t * per), k1 = std::min(words, k0 + per);
+            part[t] = checksum_range(w, k0, k1);
+        });
+    uint64_t s = 0;
+    for (int t = 0; t < threads; ++t) {
+        pool[t].join();
+        s += part[t];
+    }
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t gwas_checksum(const void *p, int64_t bytes) {
+    if (!p || bytes <= 0) return 0;
+    return checksum_range((const uint32_t *)p, 0, bytes / 4);
+}
+
+gwas_status gwas_solve(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, const double *Y,
+                       int32_t y_on_device, const double *h2, int32_t form, void *b,
+                       int32_t b_on_device, void *stream) {
+    g_err.clear();
+    gwas_status st = check_solve(c, i0, mi, tb, Y, y_on_device, h2, form);
+    if (st != GWAS_OK) return st;
+    if (mi > 0 && !b) return fail(GWAS_EINVAL, "b is NULL");
     if (mi == 0) return GWAS_OK;
     HIP_TRY(hipSetDevice(c->dev));
     hipStream_t s = (hipStream_t)stream;
-    const int p = c->p, np = c->n_pad;
+    const int p = c->p;
     const size_t besz = form == GWAS_FORM_F64 ? 8 : 4;
-
-    const void *a_base = form == GWAS_FORM_F64 ? (const void *)c->xr64
-                       : form == GWAS_FORM_F32 ? (const void *)c->xr32 : (const void *)c->xrbf;
 
     for (int j0 = 0; j0 < tb; j0 += c->tcap) {
         const int jb = std::min(c->tcap, tb - j0);
-        // traits: stage (host) and rotate y' = Z^T y in FP64
-        const double *ysrc = Y + (size_t)j0 * c->n;
-        if (!y_on_device) {
-            HIP_TRY(hipMemcpyAsync(c->y_in, ysrc, sizeof(double) * (size_t)jb * c->n,
-                                   hipMemcpyHostToDevice, s));
-            c->bytes_h2d += (int64_t)sizeof(double) * jb * c->n;
-            ysrc = c->y_in;
-        }
-        HIP_TRY(hipMemcpyAsync(c->h2, h2 + j0, sizeof(double) * jb, hipMemcpyHostToDevice, s));
-        RotOut ro{c->yt, nullptr, nullptr, 0, 0, np};
-        HIP_TRY(launch_rotate(ysrc, GWAS_DT_F64, jb, c->n, c->n, c->Z, np, ro, s));
-        PrepArgs pa{c->yt, c->h2, c->w, c->xlt, c->panels[form], c->fac, jb, c->n, np, p, c->tcap,
-                    fac_stride(p), form};
-        HIP_TRY(launch_prep(pa, s));
-
-        FusedArgs fa{};
-        fa.a = a_base;
-        fa.a_plane_rows = c->m_rows;
-        fa.panels = c->panels[form];
-        fa.tcap = c->tcap;
-        fa.fac = c->fac;
-        fa.fac_stride = fac_stride(p);
-        fa.tb = jb;
-        fa.n_pad = np;
-        fa.p = p;
-        fa.rank_rtol = kRankRtol[form];
-        fa.non_spd = c->counters;
-        fa.f32_flush = form == GWAS_FORM_F32 ? c->f32_flush : 0;
-
+        if ((st = prep_traits(c, j0, jb, Y, y_on_device, h2, form, s)) != GWAS_OK) return st;
+        FusedArgs fa = fused_args(c, jb, form);
         if (b_on_device) {
             fa.i0 = i0;
             fa.mi = mi;
             fa.b = (uint8_t *)b + (size_t)j0 * p * besz;
             fa.ldt = tb;
-            std::pair<hipEvent_t, hipEvent_t> ev{};
-            HIP_TRY(timed_begin(c, s, ev));
-            HIP_TRY(launch_fused(form, fa, s));
-            HIP_TRY(timed_end(c, s, ev, c->t_fused));
+            if ((st = launch_fused_timed(c, form, fa, s)) != GWAS_OK) return st;
         } else {
             // slabs of SNPs into two device buffers; copies out on the side stream
-            if (!c->bstage[0]) {
-                for (int u = 0; u < 2; ++u) {
-                    hipError_t e = hipMalloc(&c->bstage[u], c->bstage_bytes);
-                    if (e != hipSuccess)
-                        return fail(GWAS_ENOMEM, "b staging (%zu bytes): %s", c->bstage_bytes,
-                                    hipGetErrorString(e));
-                    c->resident += (int64_t)c->bstage_bytes;
-                }
-            }
+            if ((st = ensure_bstage(c)) != GWAS_OK) return st;
             int slot = 0;
             for (int64_t s0 = 0; s0 < mi; s0 += c->slab, slot ^= 1) {
                 const int64_t cnt = std::min<int64_t>(c->slab, mi - s0);
@@ -414,10 +489,7 @@ gwas_status gwas_solve(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, const do
                 fa.mi = cnt;
                 fa.b = c->bstage[slot];
                 fa.ldt = jb;
-                std::pair<hipEvent_t, hipEvent_t> ev{};
-                HIP_TRY(timed_begin(c, s, ev));
-                HIP_TRY(launch_fused(form, fa, s));
-                HIP_TRY(timed_end(c, s, ev, c->t_fused));
+                if ((st = launch_fused_timed(c, form, fa, s)) != GWAS_OK) return st;
                 HIP_TRY(hipEventRecord(c->ev_done[slot], s));
                 HIP_TRY(hipStreamWaitEvent(c->side, c->ev_done[slot], 0));
                 const size_t row = (size_t)jb * p * besz;
@@ -431,6 +503,97 @@ gwas_status gwas_solve(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, const do
             HIP_TRY(hipStreamWaitEvent(s, c->ev_side, 0));
         }
     }
+    c->problems += mi * (int64_t)tb;
+    return GWAS_OK;
+}
+
+gwas_status gwas_solve_stream(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, const double *Y,
+                              int32_t y_on_device, const double *h2, int32_t form, gwas_slab_fn fn,
+                              void *user, uint64_t *checksums, int64_t max_checksums, int64_t *n_slabs,
+                              void *stream) {
+    g_err.clear();
+    gwas_status st = check_solve(c, i0, mi, tb, Y, y_on_device, h2, form);
+    if (st != GWAS_OK) return st;
+    if (n_slabs) *n_slabs = 0;
+    if (mi == 0) return GWAS_OK;
+    HIP_TRY(hipSetDevice(c->dev));
+    hipStream_t s = (hipStream_t)stream;
+    const int p = c->p;
+    const size_t besz = form == GWAS_FORM_F64 ? 8 : 4;
+    if ((st = ensure_bstage(c)) != GWAS_OK) return st;
+    const int R = c->ring_slots;
+    if (c->ring.empty()) {
+        c->ring_bytes = c->bstage_bytes;
+        c->ring.assign(R, nullptr);
+        c->ring_ev.assign(R, nullptr);
+        for (int r = 0; r < R; ++r) {
+            hipError_t e = hipHostMalloc(&c->ring[r], c->ring_bytes, hipHostMallocDefault);
+            if (e != hipSuccess)
+                return fail(GWAS_ENOMEM, "pinned ring slot (%zu bytes): %s", c->ring_bytes, hipGetErrorString(e));
+            HIP_TRY(hipEventCreateWithFlags(&c->ring_ev[r], hipEventDisableTiming));
+        }
+    }
+
+    struct Pending {
+        gwas_slab slab;
+        int slot;
+    };
+    std::vector<Pending> inflight;   // issued, not yet consumed, in issue order
+    int64_t issued = 0, consumed = 0;
+    auto consume_one = [&]() -> gwas_status {
+        Pending pd = inflight.front();
+        inflight.erase(inflight.begin());
+        HIP_TRY(hipEventSynchronize(c->ring_ev[pd.slot]));
+        pd.slab.b = c->ring[pd.slot];
+        pd.slab.checksum = checksum_parallel(pd.slab.b, pd.slab.bytes, c->host_threads);
+        if (checksums && consumed < max_checksums) checksums[consumed] = pd.slab.checksum;
+        if (fn) fn(user, &pd.slab);
+        ++consumed;
+        return GWAS_OK;
+    };
+
+    int dslot = 0;
+    for (int j0 = 0; j0 < tb; j0 += c->tcap) {
+        const int jb = std::min(c->tcap, tb - j0);
+        if ((st = prep_traits(c, j0, jb, Y, y_on_device, h2, form, s)) != GWAS_OK) return st;
+        FusedArgs fa = fused_args(c, jb, form);
+        for (int64_t s0 = 0; s0 < mi; s0 += c->slab, dslot ^= 1) {
+            const int64_t cnt = std::min<int64_t>(c->slab, mi - s0);
+            const int rslot = (int)(issued % R);
+            if ((int64_t)inflight.size() >= R)   // the ring slot is still held: consume the oldest slab
+                if ((st = consume_one()) != GWAS_OK) return st;
+            HIP_TRY(hipStreamWaitEvent(s, c->ev_free[dslot], 0));
+            fa.i0 = i0 + s0;
+            fa.mi = cnt;
+            fa.b = c->bstage[dslot];
+            fa.ldt = jb;
+            if ((st = launch_fused_timed(c, form, fa, s)) != GWAS_OK) return st;
+            HIP_TRY(hipEventRecord(c->ev_done[dslot], s));
+            HIP_TRY(hipStreamWaitEvent(c->side, c->ev_done[dslot], 0));
+            const size_t bytes = (size_t)cnt * jb * p * besz;
+            HIP_TRY(hipMemcpyAsync(c->ring[rslot], c->bstage[dslot], bytes, hipMemcpyDeviceToHost, c->side));
+            HIP_TRY(hipEventRecord(c->ring_ev[rslot], c->side));
+            HIP_TRY(hipEventRecord(c->ev_free[dslot], c->side));
+            c->bytes_d2h += (int64_t)bytes;
+            Pending pd{};
+            pd.slab.index = issued;
+            pd.slab.i0 = i0 + s0;
+            pd.slab.count = cnt;
+            pd.slab.j0 = j0;
+            pd.slab.tb = jb;
+            pd.slab.p = p;
+            pd.slab.form = form;
+            pd.slab.bytes = (int64_t)bytes;
+            pd.slot = rslot;
+            inflight.push_back(pd);
+            ++issued;
+        }
+    }
+    while (!inflight.empty())
+        if ((st = consume_one()) != GWAS_OK) return st;
+    HIP_TRY(hipEventRecord(c->ev_side, c->side));
+    HIP_TRY(hipStreamWaitEvent(s, c->ev_side, 0));
+    if (n_slabs) *n_slabs = issued;
     c->problems += mi * (int64_t)tb;
     return GWAS_OK;
 }

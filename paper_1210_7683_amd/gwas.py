@@ -32,7 +32,18 @@ class Options(ctypes.Structure):
     _fields_ = [("m_capacity", ctypes.c_int64), ("forms", ctypes.c_uint32),
                 ("device", ctypes.c_int32), ("max_traits", ctypes.c_int32),
                 ("slab_snps", ctypes.c_int32), ("f32_flush", ctypes.c_int32),
-                ("timing", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
+                ("timing", ctypes.c_int32), ("ring_slots", ctypes.c_int32),
+                ("host_threads", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+
+
+class Slab(ctypes.Structure):
+    _fields_ = [("index", ctypes.c_int64), ("i0", ctypes.c_int64), ("count", ctypes.c_int64),
+                ("j0", ctypes.c_int32), ("tb", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("form", ctypes.c_int32), ("b", ctypes.c_void_p), ("bytes", ctypes.c_int64),
+                ("checksum", ctypes.c_uint64)]
+
+
+SLAB_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.POINTER(Slab))
 
 
 class Stats(ctypes.Structure):
@@ -62,6 +73,11 @@ def load():
     lib.gwas_rotate.restype = i32
     lib.gwas_solve.argtypes = [vp, i64, i64, i32, vp, i32, vp, i32, vp, i32, vp]
     lib.gwas_solve.restype = i32
+    lib.gwas_solve_stream.argtypes = [vp, i64, i64, i32, vp, i32, vp, i32, SLAB_FN, vp,
+                                      ctypes.POINTER(ctypes.c_uint64), i64, ctypes.POINTER(i64), vp]
+    lib.gwas_solve_stream.restype = i32
+    lib.gwas_checksum.argtypes = [vp, i64]
+    lib.gwas_checksum.restype = ctypes.c_uint64
     lib.gwas_copy_rotated.argtypes = [vp, i64, i64, i32, vp, i32, vp]
     lib.gwas_copy_rotated.restype = i32
     lib.gwas_stats.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -138,7 +154,8 @@ class Cohort:
 
     def __init__(self, Z, w, xl, m_capacity: int, forms=("f64", "f32", "bf16x3"),
                  max_traits: int = 1024, device: int = 0, slab_snps: int = 0,
-                 f32_flush: int | None = None, timing: bool = False):
+                 f32_flush: int | None = None, timing: bool = False, ring_slots: int = 0,
+                 host_threads: int = 0):
         lib = load()
         Z = np.asarray(Z, dtype=np.float64)
         n = Z.shape[0]
@@ -158,6 +175,8 @@ class Cohort:
         if f32_flush is not None:
             opt.f32_flush = int(f32_flush)
         opt.timing = int(bool(timing))
+        opt.ring_slots = int(ring_slots)
+        opt.host_threads = int(host_threads)
         h = ctypes.c_void_p()
         _check(lib.gwas_setup(ctypes.byref(h), n, xl.shape[0] + 1, zc.ctypes.data, w.ctypes.data,
                               xl.ctypes.data, ctypes.byref(opt)))
@@ -222,6 +241,48 @@ class Cohort:
         self._keep = (ykeep, h2)
         return out
 
+    def solve_stream(self, y, h2, form: str = "f32", i0: int = 0, m: int | None = None,
+                     on_slab=None, stream=None, max_slabs: int = 1 << 20):
+        """Streamed solve: b arrives slab by slab in pinned host memory.
+
+        on_slab(slab_info: dict, b: numpy view) is called for each slab on the
+        calling thread; the view is valid only during the call. Returns the
+        list of slab checksums (see gwas_checksum).
+        """
+        lib = load()
+        f = FORMS[form]
+        m = self.m_capacity - i0 if m is None else int(m)
+        t = int(y.shape[0])
+        h2 = np.ascontiguousarray(h2, dtype=np.float64)
+        if h2.shape != (t,):
+            raise ValueError("h2 needs one value per trait")
+        yp, ydev, ykeep = _ptr(y if _is_device(y) else np.ascontiguousarray(y, dtype=np.float64))
+        dt = np.float64 if f == FORM_F64 else np.float32
+        errors = []
+
+        def cb(_user, sp):
+            if on_slab is None:
+                return
+            try:
+                s = sp.contents
+                n_el = s.bytes // np.dtype(dt).itemsize
+                buf = (ctypes.c_char * s.bytes).from_address(s.b)
+                arr = np.frombuffer(buf, dtype=dt, count=n_el).reshape(s.count, s.tb, s.p)
+                on_slab({"index": s.index, "i0": s.i0, "count": s.count, "j0": s.j0, "tb": s.tb,
+                         "checksum": s.checksum}, arr)
+            except Exception as e:       # never propagate through the C frame
+                errors.append(e)
+
+        fn = SLAB_FN(cb)
+        sums = (ctypes.c_uint64 * max_slabs)()
+        n = ctypes.c_int64(0)
+        _check(lib.gwas_solve_stream(self._h, int(i0), m, t, yp, ydev, h2.ctypes.data, f, fn, None,
+                                     sums, max_slabs, ctypes.byref(n), _stream_ptr(stream)))
+        if errors:
+            raise errors[0]
+        del ykeep
+        return [int(sums[k]) for k in range(min(n.value, max_slabs))]
+
     def copy_rotated(self, i0: int, m: int, form: str = "f64"):
         """Rotated SNP columns [i0, i0+m) from the resident store (numpy, [m][n])."""
         f = FORMS[form]
@@ -254,6 +315,12 @@ class Cohort:
     def _sync(self, stream):
         import torch
         (stream or torch.cuda.current_stream()).synchronize()
+
+
+def checksum(arr) -> int:
+    """The slab checksum of gwas_solve_stream, computed by the library on host memory."""
+    a = np.ascontiguousarray(arr)
+    return int(load().gwas_checksum(a.ctypes.data, a.nbytes))
 
 
 def version() -> str:

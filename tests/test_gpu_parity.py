@@ -203,3 +203,31 @@ def test_paper_shape_sampled_against_oracle(paper_m1e5, form, torch_cuda):
     print("paper_m1e5 %s sampled %d: max %.3e median %.3e" % (form, err.size, err.max(), np.median(err)))
     assert err.max() <= TOL[form]
     assert bool(torch_cuda.isfinite(b).all())
+
+
+def _checksum_numpy(a):
+    """Sum over the 32-bit words w_k of (k + 1) w_k, modulo 2^64 (numpy wraps uint64)."""
+    w = np.ascontiguousarray(a).view(np.uint32).astype(np.uint64)
+    return int((w * np.arange(1, w.size + 1, dtype=np.uint64)).sum(dtype=np.uint64))
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_streamed_slabs_match_resident_b_and_checksums(form, torch_cuda):
+    """b streamed through the pinned ring equals, slab by slab, the b computed resident in HBM."""
+    phi, xl, xr, y, h2 = synth.small(128, 4, 700, 45, seed=13)
+    c = cohort(phi, xl, xr, forms=(form,), slab_snps=160, max_traits=16, ring_slots=3, host_threads=3)
+    dev = c.solve(y, h2, form=form).cpu().numpy()
+    seen = []
+
+    def on_slab(info, arr):
+        ref = dev[info["i0"]:info["i0"] + info["count"], info["j0"]:info["j0"] + info["tb"]]
+        assert np.array_equal(arr, ref)
+        assert info["checksum"] == _checksum_numpy(ref)
+        seen.append((info["i0"], info["j0"]))
+
+    sums = c.solve_stream(y, h2, form=form, on_slab=on_slab)
+    assert len(sums) == len(seen) == 5 * 3              # 5 SNP slabs x 3 trait sub-blocks
+    assert len(set(seen)) == len(seen)
+    from paper_1210_7683_amd import gwas
+    assert gwas.checksum(dev[:160, :16]) == _checksum_numpy(dev[:160, :16]) == sums[0]
+    c.close()
