@@ -207,7 +207,7 @@ def test_paper_shape_sampled_against_oracle(paper_m1e5, form, torch_cuda):
 
 def _checksum_numpy(a):
     """Sum over the 32-bit words w_k of (k + 1) w_k, modulo 2^64 (numpy wraps uint64)."""
-    w = np.ascontiguousarray(a).view(np.uint32).astype(np.uint64)
+    w = np.ascontiguousarray(a).reshape(-1).view(np.uint32).astype(np.uint64)
     return int((w * np.arange(1, w.size + 1, dtype=np.uint64)).sum(dtype=np.uint64))
 
 
