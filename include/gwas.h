@@ -227,6 +227,99 @@ void gwas_destroy(gwas_ctx *ctx);
 /* Message of the last failure on this thread ("" if none). */
 const char *gwas_last_error(void);
 
+/*
+ * Serving: continuous batching of trait-block requests over a resident cohort.
+ *
+ * A server owns a scheduler thread and a consumer thread. Submitted requests
+ * wait in FIFO order until a slot is free and their device memory (rotated
+ * traits, panels, factors, two b staging buffers) fits in the server's HBM
+ * budget; they are then admitted, their traits rotated and prepared, and
+ * their SNP range is cut into work items (slabs). Every scheduling round
+ * takes the next slab of each admitted request and runs all of them in one
+ * launch, whatever their trait count and covariate count; requests that
+ * arrive meanwhile join the next round. Each slab's b is copied to the host
+ * on a second stream: into the request's own buffer when it gave one, else
+ * through a ring of pinned host slots where it is checksummed (the checksum
+ * of gwas_solve_stream) and passed to the request's callback, if any.
+ * A request's results do not depend on what else is in flight: every problem
+ * is computed by the same tile code in the same order, alone or in a mix.
+ * Requests use covariate-count prefixes of the cohort's covariates: a request
+ * with p columns uses the intercept-first X_L columns 0 .. p-2.
+ */
+typedef struct gwas_server gwas_server;
+
+typedef struct gwas_server_options {
+    int64_t hbm_budget;  /* device bytes admitted requests may hold at once; 0: 8 GiB      */
+    int32_t max_slots;   /* requests in flight at once, 1..32; 0: 8                        */
+    int32_t form;        /* GWAS_FORM_* used for every request (must be resident)          */
+    int32_t item_problems; /* target problems (SNPs x traits) per work item; 0: 4194304    */
+    int32_t max_traits;  /* largest request trait count accepted; 0: 1024                  */
+    int32_t ring_slots;  /* pinned host ring slots; 0: 2 x max_slots                       */
+    int32_t host_threads;/* checksum threads per slab; 0: 8                               */
+    int32_t reserved[6];
+} gwas_server_options;
+
+typedef struct gwas_request {
+    int32_t t;           /* traits, 1 .. max_traits                                       */
+    int32_t p;           /* design width, 2 .. min(8, the cohort's p)                      */
+    const double *Y;     /* host, n x t column-major (copied at submit)                    */
+    const double *h2;    /* host, t values (copied at submit)                              */
+    int64_t i0, m;       /* SNP range [i0, i0 + m); m = 0: all of [i0, m_capacity)        */
+    void *b;             /* host output m x t x p (FP64 for the FP64 form, else FP32), kept
+                            valid until the request completes; NULL: slabs go through the
+                            pinned ring and the callback                                  */
+    gwas_slab_fn fn;     /* called on the consumer thread for each ring slab; may be NULL  */
+    void *user;
+} gwas_request;
+
+#define GWAS_REQ_QUEUED 0
+#define GWAS_REQ_RUNNING 1
+#define GWAS_REQ_DONE 2
+#define GWAS_REQ_CANCELLED 3
+#define GWAS_REQ_FAILED 4
+
+typedef struct gwas_result {
+    int32_t state;       /* GWAS_REQ_*                                                     */
+    int32_t error;       /* gwas_status when FAILED                                       */
+    double t_submit;     /* gwas_clock() at submit                                         */
+    double t_admit;      /* when admitted (0 if never)                                     */
+    double t_done;       /* when the last slab reached the host (0 if not done)            */
+    int64_t problems;    /* m x t                                                         */
+    int64_t slabs;       /* work items                                                    */
+    uint64_t checksum;   /* sum of the ring slabs' checksums (0 with a caller buffer)      */
+    int64_t reserved[4];
+} gwas_result;
+
+/* Seconds on the steady clock used for request timestamps. */
+double gwas_clock(void);
+
+/*
+ * Create a server on a context whose cohort (rotated SNPs in opt->form) stays
+ * resident. The context must outlive the server, and must not be used by
+ * other calls while the server runs. Allocates the HBM budget as one arena and
+ * the pinned ring up front. Errors: GWAS_EINVAL (form not resident, p of the
+ * cohort above 8 is fine but requests are limited to p <= 8), GWAS_ENOMEM.
+ */
+gwas_status gwas_server_create(gwas_ctx *ctx, const gwas_server_options *opt, gwas_server **srv);
+
+/* Queue a request (non-blocking); *ticket identifies it. Errors: GWAS_EINVAL
+ * (t, p, range, h2, non-finite Y; or the request could never fit the budget). */
+gwas_status gwas_server_submit(gwas_server *srv, const gwas_request *req, uint64_t *ticket);
+
+/* State and timestamps of a request (non-blocking). GWAS_EINVAL for an unknown ticket. */
+gwas_status gwas_server_poll(gwas_server *srv, uint64_t ticket, gwas_result *out);
+
+/* Wait until the request is DONE, CANCELLED or FAILED, or timeout_s elapses
+ * (timeout_s < 0: no limit); returns GWAS_EBUSY on timeout. */
+gwas_status gwas_server_wait(gwas_server *srv, uint64_t ticket, double timeout_s, gwas_result *out);
+
+/* Cancel a request: a queued one is dropped, a running one stops issuing
+ * slabs and completes as CANCELLED once its slabs in flight have landed. */
+gwas_status gwas_server_cancel(gwas_server *srv, uint64_t ticket);
+
+/* Cancel what is queued, finish what is running, stop the threads, free. */
+gwas_status gwas_server_destroy(gwas_server *srv);
+
 /* Library version string. */
 const char *gwas_version(void);
 

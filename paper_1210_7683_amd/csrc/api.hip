@@ -9,82 +9,16 @@
 #include <thread>
 #include <vector>
 
-#include "gwas_internal.h"
+#include "ctx.h"
 
 using namespace gw;
 
-namespace {
-
-thread_local std::string g_err;
-
-gwas_status fail(gwas_status st, const char *fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_err = buf;
-    return st;
+namespace gw {
+std::string &last_error() {
+    thread_local std::string e;
+    return e;
 }
-
-#define HIP_TRY(expr)                                                                     \
-    do {                                                                                  \
-        hipError_t e_ = (expr);                                                           \
-        if (e_ != hipSuccess)                                                             \
-            return fail(e_ == hipErrorOutOfMemory ? GWAS_ENOMEM : GWAS_EHIP, "%s: %s (%d)", \
-                        #expr, hipGetErrorString(e_), (int)e_);                           \
-    } while (0)
-
-int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
-
-}  // namespace
-
-struct gwas_ctx {
-    int dev = 0;
-    int n = 0, n_pad = 0, p = 0;
-    int64_t m_cap = 0;       // SNPs the store holds
-    int64_t m_rows = 0;      // rows allocated per plane (>= m_cap)
-    uint32_t forms = 0;
-    int tcap = 0;            // traits per internal sub-block
-    int slab = 0;            // SNPs per D2H slab
-    int f32_flush = 0;
-    double w_min = 0.0;
-
-    double *Z = nullptr;     // [n_pad][n_pad]: row k = eigenvector k (zeros beyond n)
-    double *w = nullptr;     // [n_pad]
-    double *xlt = nullptr;   // [p-1][n_pad]
-    double *xr64 = nullptr;  // [m_rows][n_pad]
-    float *xr32 = nullptr;   // [m_rows][n_pad]
-    uint16_t *xrbf = nullptr;  // 4 planes [m_rows][n_pad]
-
-    double *y_in = nullptr;  // [tcap][n] staging of host traits
-    double *yt = nullptr;    // [tcap][n_pad]
-    double *h2 = nullptr;    // [tcap]
-    void *panels[3] = {nullptr, nullptr, nullptr};  // per form
-    double *fac = nullptr;   // [tcap][fac_stride]
-    unsigned long long *counters = nullptr;  // [0] non-SPD problems
-
-    void *stage = nullptr;   // rotation staging for host SNP blocks
-    size_t stage_bytes = 0;
-    void *bstage[2] = {nullptr, nullptr};
-    size_t bstage_bytes = 0;
-    hipStream_t side = nullptr;
-    hipEvent_t ev_done[2] = {nullptr, nullptr};   // slab computed
-    hipEvent_t ev_free[2] = {nullptr, nullptr};   // slab copied out
-    hipEvent_t ev_side = nullptr;
-
-    // streamed sink: pinned host ring
-    int ring_slots = 4, host_threads = 8;
-    std::vector<void *> ring;
-    size_t ring_bytes = 0;
-    std::vector<hipEvent_t> ring_ev;
-
-    int64_t snps_rotated = 0, problems = 0, bytes_h2d = 0, bytes_d2h = 0, resident = 0;
-
-    // optional per-launch timing: event pairs recorded around launches
-    bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> t_fused, t_rot, t_pool;
-};
+}  // namespace gw
 
 namespace {
 
@@ -185,7 +119,7 @@ hipError_t launch_fused(int form, const FusedArgs &a, hipStream_t s) {
 
 extern "C" {
 
-const char *gwas_last_error(void) { return g_err.c_str(); }
+const char *gwas_last_error(void) { return last_error().c_str(); }
 
 const char *gwas_version(void) { return "libgwas 0.1 (gfx950)"; }
 
@@ -201,7 +135,7 @@ void gwas_default_options(gwas_options *opt) {
 
 gwas_status gwas_setup(gwas_ctx **out, int32_t n, int32_t p, const double *Z, const double *w,
                        const double *X_L, const gwas_options *opt) {
-    g_err.clear();
+    last_error().clear();
     if (!out) return fail(GWAS_EINVAL, "ctx pointer is NULL");
     *out = nullptr;
     if (n < 1 || n > 16384) return fail(GWAS_EINVAL, "n = %d outside [1, 16384]", n);
@@ -303,7 +237,7 @@ gwas_status gwas_setup(gwas_ctx **out, int32_t n, int32_t p, const double *Z, co
 
 gwas_status gwas_rotate(gwas_ctx *c, int64_t m0, int64_t mb, const void *X, int32_t dtype,
                         int32_t on_device, void *stream) {
-    g_err.clear();
+    last_error().clear();
     if (!c) return fail(GWAS_EINVAL, "ctx is NULL");
     if (m0 < 0 || mb < 0 || m0 + mb > c->m_cap)
         return fail(GWAS_EINVAL, "SNP range [%lld, %lld) outside capacity %lld", (long long)m0,
@@ -420,32 +354,6 @@ gwas_status ensure_bstage(gwas_ctx *c) {
     return GWAS_OK;
 }
 
-uint64_t checksum_range(const uint32_t *w, int64_t k0, int64_t k1) {
-    uint64_t s = 0;
-    for (int64_t k = k0; k < k1; ++k) s += (uint64_t)(k + 1) * (uint64_t)w[k];
-    return s;
-}
-
-uint64_t checksum_parallel(const void *p, int64_t bytes, int threads) {
-    const uint32_t *w = (const uint32_t *)p;
-    const int64_t words = bytes / 4;
-    if (threads <= 1 || words < (1 << 20)) return checksum_range(w, 0, words);
-    std::vector<uint64_t> part(threads, 0);
-    std::vector<std::thread> pool;
-    const int64_t per = (words + threads - 1) / threads;
-    for (int t = 0; t < threads; ++t)
-        pool.emplace_back([&, t] {
-            const int64_t k0 = std::min(words, t * per), k1 = std::min(words, k0 + per);
-            part[t] = checksum_range(w, k0, k1);
-        });
-    uint64_t s = 0;
-    for (int t = 0; t < threads; ++t) {
-        pool[t].join();
-        s += part[t];
-    }
-    return s;
-}
-
 }  // namespace
 
 extern "C" {
@@ -458,7 +366,7 @@ uint64_t gwas_checksum(const void *p, int64_t bytes) {
 gwas_status gwas_solve(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, const double *Y,
                        int32_t y_on_device, const double *h2, int32_t form, void *b,
                        int32_t b_on_device, void *stream) {
-    g_err.clear();
+    last_error().clear();
     gwas_status st = check_solve(c, i0, mi, tb, Y, y_on_device, h2, form);
     if (st != GWAS_OK) return st;
     if (mi > 0 && !b) return fail(GWAS_EINVAL, "b is NULL");
@@ -511,7 +419,7 @@ gwas_status gwas_solve_stream(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, c
                               int32_t y_on_device, const double *h2, int32_t form, gwas_slab_fn fn,
                               void *user, uint64_t *checksums, int64_t max_checksums, int64_t *n_slabs,
                               void *stream) {
-    g_err.clear();
+    last_error().clear();
     gwas_status st = check_solve(c, i0, mi, tb, Y, y_on_device, h2, form);
     if (st != GWAS_OK) return st;
     if (n_slabs) *n_slabs = 0;
@@ -600,7 +508,7 @@ gwas_status gwas_solve_stream(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, c
 
 gwas_status gwas_copy_rotated(gwas_ctx *c, int64_t i0, int64_t mi, int32_t form, void *dst,
                               int32_t dst_on_device, void *stream) {
-    g_err.clear();
+    last_error().clear();
     if (!c) return fail(GWAS_EINVAL, "ctx is NULL");
     if (form != GWAS_FORM_F64 && form != GWAS_FORM_F32)
         return fail(GWAS_EINVAL, "copy_rotated supports the FP64 and FP32 stores only");
@@ -620,7 +528,7 @@ gwas_status gwas_copy_rotated(gwas_ctx *c, int64_t i0, int64_t mi, int32_t form,
 }
 
 gwas_status gwas_stats(gwas_ctx *c, gwas_stats_t *out) {
-    g_err.clear();
+    last_error().clear();
     if (!c || !out) return fail(GWAS_EINVAL, "NULL pointer");
     HIP_TRY(hipSetDevice(c->dev));
     HIP_TRY(hipDeviceSynchronize());
@@ -651,7 +559,7 @@ gwas_status gwas_stats(gwas_ctx *c, gwas_stats_t *out) {
 }
 
 gwas_status gwas_reset_stats(gwas_ctx *c) {
-    g_err.clear();
+    last_error().clear();
     if (!c) return fail(GWAS_EINVAL, "NULL pointer");
     HIP_TRY(hipSetDevice(c->dev));
     HIP_TRY(hipDeviceSynchronize());
@@ -678,7 +586,7 @@ int64_t gwas_debug_size(gwas_ctx *c, int32_t what, int32_t form) {
 }
 
 gwas_status gwas_debug_copy(gwas_ctx *c, int32_t what, int32_t form, void *dst, int64_t bytes) {
-    g_err.clear();
+    last_error().clear();
     const int64_t need = gwas_debug_size(c, what, form);
     if (need < 0 || !dst || bytes != need) return fail(GWAS_EINVAL, "bad debug request");
     const void *src = what == GWAS_DBG_XL ? (const void *)c->xlt

@@ -81,18 +81,19 @@ struct FusedCfg {
 template <typename T>
 __device__ __forceinline__ T load16(const uint8_t *p) { return *(const T *)p; }
 
+// One TM x TN tile of problems (tile index over the tiles of a, traits fastest),
+// computed by a whole workgroup of C::NT threads with `lds` (C::LDS bytes) as
+// its staging memory. Every thread of the workgroup must call it with the same
+// arguments (it contains workgroup barriers).
 template <int FORM, int P, bool FLUSH, class T>
-__global__ __launch_bounds__((FusedCfg<FORM, P, T>::NT)) void fused_kernel(FusedArgs a) {
+__device__ __forceinline__ void fused_tile(const FusedArgs &a, int64_t tile, uint8_t *lds) {
     using C = FusedCfg<FORM, P, T>;
     constexpr int NQ = C::NQ, TM = C::TM, TN = C::TN, NT = C::NT;
     constexpr int FM = C::FM, FN = C::FN, WM = C::WM;
     constexpr int SPR = C::SPR, RS = C::RS, CB = C::CB;
     using acc_t = typename std::conditional<FORM == GWAS_FORM_F64, d4, f4>::type;
 
-    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-
     const int ntn = (a.tb + TN - 1) / TN;
-    const int64_t tile = blockIdx.x;
     const int tn = (int)(tile % ntn);
     const int64_t tm = tile / ntn;
     const int64_t m_base = tm * TM;
@@ -381,6 +382,12 @@ __global__ __launch_bounds__((FusedCfg<FORM, P, T>::NT)) void fused_kernel(Fused
             }
         }
     if (bad) atomicAdd(a.non_spd, (unsigned long long)bad);
+}
+
+template <int FORM, int P, bool FLUSH, class T>
+__global__ __launch_bounds__((FusedCfg<FORM, P, T>::NT)) void fused_kernel(FusedArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    fused_tile<FORM, P, FLUSH, T>(a, blockIdx.x, lds);
 }
 
 template <int FORM, int P, bool FLUSH, class T = typename DefaultTile<FORM, P, FLUSH>::type>

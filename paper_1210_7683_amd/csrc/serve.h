@@ -1,0 +1,38 @@
+// Grouped launch of the serving loop (work items of several requests in one launch).
+#pragma once
+
+#include "gwas_internal.h"
+
+namespace gw {
+
+constexpr int kServeMaxP = 8;       // largest design width a request may use
+constexpr int kServeMaxItems = 32;  // work items per launch (one per admitted request)
+
+// One work item: a slab of SNPs of one request against all its traits.
+struct ServeItem {
+    const void *panels;   // the request's trait panels (plane stride tcap = tb rows)
+    const double *fac;    // its per-trait factors
+    void *b;              // device staging for the slab's b: mi x tb x p
+    int64_t i0, mi;       // SNP range
+    int64_t tile0;        // first tile index of this item within the launch
+    int32_t tb, p, tcap, fac_stride;
+};
+
+struct ServeBatch {
+    const void *a;               // resident rotated SNPs of the form
+    int64_t a_plane_rows;
+    unsigned int *counter;       // tile counter, zero at launch
+    unsigned long long *non_spd;
+    int64_t total_tiles;
+    double rank_rtol;
+    int32_t n_pad, f32_flush, n_items, pad_;
+    ServeItem items[kServeMaxItems];
+};
+
+// Tile shape (SNPs x traits per tile) of the serving kernel for a form and p.
+void serve_tile_shape(int form, bool flush, int p, int &tm, int &tn);
+
+// Launch `grid` persistent workgroups over the batch's tiles.
+hipError_t launch_serve(int form, bool flush, const ServeBatch &bt, int grid, hipStream_t s);
+
+}  // namespace gw

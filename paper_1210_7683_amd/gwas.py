@@ -46,6 +46,28 @@ class Slab(ctypes.Structure):
 SLAB_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.POINTER(Slab))
 
 
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_int64), ("max_slots", ctypes.c_int32), ("form", ctypes.c_int32),
+                ("item_problems", ctypes.c_int32), ("max_traits", ctypes.c_int32),
+                ("ring_slots", ctypes.c_int32), ("host_threads", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int32), ("p", ctypes.c_int32), ("Y", ctypes.c_void_p),
+                ("h2", ctypes.c_void_p), ("i0", ctypes.c_int64), ("m", ctypes.c_int64),
+                ("b", ctypes.c_void_p), ("fn", ctypes.c_void_p), ("user", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("error", ctypes.c_int32), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("problems", ctypes.c_int64),
+                ("slabs", ctypes.c_int64), ("checksum", ctypes.c_uint64), ("reserved", ctypes.c_int64 * 4)]
+
+
+REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "cancelled", 4: "failed"}
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("non_spd", ctypes.c_int64), ("snps_rotated", ctypes.c_int64),
                 ("problems", ctypes.c_int64), ("bytes_h2d", ctypes.c_int64),
@@ -78,6 +100,20 @@ def load():
     lib.gwas_solve_stream.restype = i32
     lib.gwas_checksum.argtypes = [vp, i64]
     lib.gwas_checksum.restype = ctypes.c_uint64
+    lib.gwas_clock.argtypes = []
+    lib.gwas_clock.restype = ctypes.c_double
+    lib.gwas_server_create.argtypes = [vp, ctypes.POINTER(ServerOptions), ctypes.POINTER(vp)]
+    lib.gwas_server_create.restype = i32
+    lib.gwas_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    lib.gwas_server_submit.restype = i32
+    lib.gwas_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Result)]
+    lib.gwas_server_poll.restype = i32
+    lib.gwas_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(Result)]
+    lib.gwas_server_wait.restype = i32
+    lib.gwas_server_cancel.argtypes = [vp, ctypes.c_uint64]
+    lib.gwas_server_cancel.restype = i32
+    lib.gwas_server_destroy.argtypes = [vp]
+    lib.gwas_server_destroy.restype = i32
     lib.gwas_copy_rotated.argtypes = [vp, i64, i64, i32, vp, i32, vp]
     lib.gwas_copy_rotated.restype = i32
     lib.gwas_stats.argtypes = [vp, ctypes.POINTER(Stats)]
@@ -315,6 +351,103 @@ class Cohort:
     def _sync(self, stream):
         import torch
         (stream or torch.cuda.current_stream()).synchronize()
+
+
+class Server:
+    """Continuous-batching server over a resident Cohort (gwas_server_* in gwas.h).
+
+    submit() copies the traits and returns a ticket at once; requests that
+    arrive while others are on the GPU are admitted as slots and the HBM budget
+    free up, and each scheduling round runs one slab of every admitted request
+    in a single launch.
+    """
+
+    def __init__(self, cohort: "Cohort", form: str = "f32", hbm_budget: int = 0, max_slots: int = 0,
+                 item_problems: int = 0, max_traits: int = 0, ring_slots: int = 0, host_threads: int = 0):
+        lib = load()
+        opt = ServerOptions()
+        opt.hbm_budget = int(hbm_budget)
+        opt.max_slots = int(max_slots)
+        opt.form = FORMS[form]
+        opt.item_problems = int(item_problems)
+        opt.max_traits = int(max_traits)
+        opt.ring_slots = int(ring_slots)
+        opt.host_threads = int(host_threads)
+        h = ctypes.c_void_p()
+        _check(lib.gwas_server_create(cohort._h, ctypes.byref(opt), ctypes.byref(h)))
+        self._h = h
+        self.cohort = cohort
+        self.form = form
+        self._outs = {}
+
+    def submit(self, y, h2, p: int, out=None, i0: int = 0, m: int = 0) -> int:
+        """Queue a request: traits y [t][n], h2 [t], design width p (intercept-first
+        covariate prefix). out: host array/tensor [m][t][p] kept until completion,
+        or None (b streams through the pinned ring and is checksummed)."""
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        h2 = np.ascontiguousarray(h2, dtype=np.float64)
+        r = Request()
+        r.t = int(y.shape[0])
+        r.p = int(p)
+        r.Y = y.ctypes.data
+        r.h2 = h2.ctypes.data
+        r.i0 = int(i0)
+        r.m = int(m)
+        keep = None
+        if out is not None:
+            bp, dev, keep = _ptr(out)
+            if dev:
+                raise ValueError("a request's output must be host memory")
+            r.b = bp.value
+        tk = ctypes.c_uint64()
+        _check(load().gwas_server_submit(self._h, ctypes.byref(r), ctypes.byref(tk)))
+        if keep is not None:
+            self._outs[tk.value] = keep
+        return tk.value
+
+    @staticmethod
+    def _res(res: Result) -> dict:
+        return {"state": REQ_STATES[res.state], "error": res.error, "t_submit": res.t_submit,
+                "t_admit": res.t_admit, "t_done": res.t_done, "problems": res.problems,
+                "slabs": res.slabs, "checksum": int(res.checksum)}
+
+    def poll(self, ticket: int) -> dict:
+        res = Result()
+        _check(load().gwas_server_poll(self._h, int(ticket), ctypes.byref(res)))
+        return self._res(res)
+
+    def wait(self, ticket: int, timeout: float | None = None) -> dict:
+        res = Result()
+        _check(load().gwas_server_wait(self._h, int(ticket), -1.0 if timeout is None else float(timeout),
+                                       ctypes.byref(res)))
+        self._outs.pop(int(ticket), None)
+        return self._res(res)
+
+    def cancel(self, ticket: int):
+        _check(load().gwas_server_cancel(self._h, int(ticket)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(load().gwas_server_destroy(self._h))
+            self._h = None
+            self._outs.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def clock() -> float:
+    """The library's steady clock (seconds), the time base of request timestamps."""
+    return float(load().gwas_clock())
 
 
 def checksum(arr) -> int:

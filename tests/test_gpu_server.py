@@ -1,0 +1,133 @@
+"""The continuous-batching server: parity, alone-vs-mix identity, admission, cancellation.
+
+Requests carry their own traits, heritabilities and covariate count p (a
+prefix of the cohort's intercept-first covariates). Each result is checked
+against the FP64 oracle, and a request's b is required to be bitwise the same
+when it runs alone and when it runs in a mix with other requests.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_common import TOL, scaled_err
+
+pytestmark = pytest.mark.gpu
+
+N, PMAX, M = 128, 8, 700
+
+
+@pytest.fixture(scope="module")
+def cohort_f32():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1210_7683_amd import gwas
+    phi, xl, xr, _, _ = synth.small(N, PMAX, M, 1, seed=41)
+    w, z = np.linalg.eigh(phi)
+    c = gwas.Cohort(z, w, xl, M, forms=("f32", "bf16x3"))
+    c.rotate(0, xr)
+    yield dict(c=c, phi=phi, xl=xl, xr=xr)
+    c.close()
+
+
+def _requests(seed, count):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        t = int(rng.choice([1, 3, 17, 40, 64]))
+        p = int(rng.integers(2, PMAX + 1))
+        out.append((rng.standard_normal((t, N)), rng.uniform(0.1, 0.9, t), p))
+    return out
+
+
+def _run(server, reqs, together):
+    outs, tickets = [], []
+    for y, h2, p in reqs:
+        out = np.empty((M, y.shape[0], p), dtype=np.float32)
+        tk = server.submit(y, h2, p, out=out)
+        if not together:
+            assert server.wait(tk, timeout=60)["state"] == "done"
+        outs.append(out)
+        tickets.append(tk)
+    res = [server.wait(tk, timeout=60) for tk in tickets]
+    assert all(r["state"] == "done" for r in res), res
+    return outs, res
+
+
+@pytest.mark.parametrize("form", ["f32", "bf16x3"])
+def test_alone_equals_mix_and_matches_oracle(cohort_f32, form):
+    from paper_1210_7683_amd import gwas
+    d = cohort_f32
+    reqs = _requests(1, 7)
+    with gwas.Server(d["c"], form=form, max_slots=4, item_problems=6000) as srv:
+        alone, _ = _run(srv, reqs, together=False)
+        mix, res = _run(srv, reqs, together=True)
+    for a, b in zip(alone, mix):
+        assert np.array_equal(a, b)
+    # overlap: in the mix, some request was admitted before another finished
+    spans = sorted((r["t_admit"], r["t_done"]) for r in res)
+    assert any(spans[k + 1][0] < spans[k][1] for k in range(len(spans) - 1))
+    for (y, h2, p), b in zip(reqs, alone):
+        ref = oracle.gls_grid(d["phi"], d["xl"][: p - 1], d["xr"], y, h2)
+        err = scaled_err(b, ref)
+        assert err.max() <= TOL[form], (p, y.shape[0], err.max())
+
+
+def test_ring_checksums(cohort_f32):
+    from paper_1210_7683_amd import gwas
+    d = cohort_f32
+    reqs = _requests(2, 4)
+    with gwas.Server(d["c"], form="f32", max_slots=3, item_problems=5000) as srv:
+        ref, _ = _run(srv, reqs, together=False)
+        tickets = [srv.submit(y, h2, p) for y, h2, p in reqs]
+        res = [srv.wait(tk, timeout=60) for tk in tickets]
+    for (y, h2, p), b, r in zip(reqs, ref, res):
+        t = y.shape[0]
+        slab = min(M, max(256, 5000 // t // 256 * 256))
+        expect = 0
+        for s0 in range(0, M, slab):
+            expect = (expect + gwas.checksum(b[s0:s0 + slab])) % (1 << 64)
+        assert r["state"] == "done" and r["slabs"] == -(-M // slab)
+        assert r["checksum"] == expect
+
+
+def test_admission_by_memory_serialises_requests(cohort_f32):
+    from paper_1210_7683_amd import gwas
+    d = cohort_f32
+    reqs = [(y, h2, 4) for y, h2, _ in _requests(3, 4)]
+    t_max = max(y.shape[0] for y, _, _ in reqs)
+    # a budget that holds one request at a time (the largest needs < 4 MB here)
+    with gwas.Server(d["c"], form="f32", max_slots=8, hbm_budget=4 << 20, item_problems=6000) as srv:
+        outs, res = _run(srv, reqs, together=True)
+    spans = sorted((r["t_admit"], r["t_done"]) for r in res)
+    for k in range(len(spans) - 1):
+        assert spans[k + 1][0] >= spans[k][1]
+    assert t_max <= 64
+
+
+def test_cancel_and_errors(cohort_f32):
+    from paper_1210_7683_amd import gwas
+    d = cohort_f32
+    y = np.random.default_rng(0).standard_normal((64, N))
+    h2 = np.full(64, 0.5)
+    with gwas.Server(d["c"], form="f32", max_slots=1, item_problems=2000) as srv:
+        first = srv.submit(y, h2, 8)
+        queued = srv.submit(y, h2, 8)
+        srv.cancel(queued)
+        srv.cancel(first)
+        assert srv.wait(queued, timeout=60)["state"] == "cancelled"
+        assert srv.wait(first, timeout=60)["state"] in ("cancelled", "done")
+        for bad in [dict(p=1), dict(p=PMAX + 1), dict(m=M + 1), dict(i0=M)]:
+            args = dict(p=4)
+            args.update(bad)
+            with pytest.raises(gwas.GwasError):
+                srv.submit(y, h2, **args)
+        with pytest.raises(gwas.GwasError):
+            srv.submit(y, np.full(64, 1.5), 4)
+        with pytest.raises(gwas.GwasError):
+            srv.poll(12345)
+    with pytest.raises(gwas.GwasError):
+        gwas.Server(d["c"], form="f64")          # form not resident
+    with gwas.Server(d["c"], form="f32", hbm_budget=1 << 16) as small:
+        with pytest.raises(gwas.GwasError):       # can never fit the budget
+            small.submit(y, h2, 4)
