@@ -129,6 +129,65 @@ def stream_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def serve_bench(args):
+    """Serving: resident cohort n = 1000, m = 1e6; Poisson arrivals; each request a
+    trait block with t ~ log-uniform[1, 512], its own h2 and p - 1 ~ U{1..7}; b
+    streamed to pinned host memory and checksummed; p50/p99 latency at a fixed rate."""
+    import torch
+
+    import synth
+    from paper_1210_7683_amd import gwas
+
+    w = synth.WORKLOADS[args.workload]
+    form = args.forms.split(",")[0]
+    t0 = time.perf_counter()
+    phi, xl = synth.kinship(w), synth.covariates(w)       # intercept + 6 covariates: p up to 8
+    xr = synth.snps(w)
+    ev, z = np.linalg.eigh(phi)
+    reqs = synth.requests(w, args.warmup_requests + args.requests, args.rate)
+    log("inputs drawn in %.1f s; %d requests at %.1f/s" % (time.perf_counter() - t0, len(reqs), args.rate))
+    cohort = gwas.Cohort(z, ev, xl, w.m, forms=(form,))
+    xr_d = torch.from_numpy(xr).cuda()
+    cohort.rotate(0, xr_d)
+    torch.cuda.synchronize()
+    del xr_d
+    srv = gwas.Server(cohort, form=form, max_slots=args.slots, max_traits=512,
+                      host_threads=min(16, os.cpu_count() or 1))
+    start = gwas.clock() + 0.2
+    tickets = []
+    for r in reqs:
+        delay = start + r.arrival_s - gwas.clock()
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.submit(r.y, r.h2, r.p))
+    res = [srv.wait(tk, timeout=600) for tk in tickets]
+    srv.close()
+    cohort.close()
+    meas = list(range(args.warmup_requests, len(reqs)))
+    lat = np.array([res[k]["t_done"] - (start + reqs[k].arrival_s) for k in meas])
+    qwait = np.array([res[k]["t_admit"] - (start + reqs[k].arrival_s) for k in meas])
+    problems = sum(res[k]["problems"] for k in meas)
+    bytes_b = sum(res[k]["problems"] * reqs[k].p * (8 if form == "f64" else 4) for k in meas)
+    t_first = start + reqs[meas[0]].arrival_s
+    t_last = max(res[k]["t_done"] for k in meas)
+    span = t_last - t_first
+    ok = all(res[k]["state"] == "done" for k in range(len(reqs)))
+    line = {
+        "metric": "serving: p50/p99 latency and GLS problems/s at a fixed arrival rate",
+        "value": problems / span, "unit": "GLS problems/s", "n_gpus": 1, "dtype": form,
+        "config": {"workload": w.name, "n": w.n, "m": w.m, "rate_hz": args.rate,
+                   "requests": len(meas), "warmup_requests": args.warmup_requests, "slots": args.slots,
+                   "t": "log-uniform[1,512]", "p": "2..8", "form": form},
+        "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+        "latency_max_s": float(lat.max()), "queue_wait_p99_s": float(np.percentile(qwait, 99)),
+        "mean_traits": float(np.mean([reqs[k].y.shape[0] for k in meas])),
+        "d2h_gbps": bytes_b / span / 1e9, "window_s": span, "all_done": ok,
+    }
+    log("serving at %.1f req/s: p50 %.3f s, p99 %.3f s, %.3e GLS/s, b to host %.1f GB/s" %
+        (args.rate, line["latency_p50_s"], line["latency_p99_s"], line["value"], line["d2h_gbps"]))
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +198,10 @@ def main():
     ap.add_argument("--f32-flush", type=int, default=None,
                     help="FP32 form: FP64 fold interval in chunks of 16 samples (library default 2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rate", type=float, default=16.0, help="serving: request arrival rate (1/s)")
+    ap.add_argument("--requests", type=int, default=200, help="serving: measured requests")
+    ap.add_argument("--warmup-requests", type=int, default=20)
+    ap.add_argument("--slots", type=int, default=8, help="serving: requests in flight")
     ap.add_argument("--profile-pass", action="store_true",
                     help="one step of the headline form plus a plain 1 GiB device copy (for counter "
                          "calibration), no timing output; meant to run under rocprofv3")
@@ -159,6 +222,10 @@ def main():
         if args.forms == "f32,f64,bf16x3":
             args.forms = "bf16x3"
         return stream_bench(args)
+    if args.workload.startswith("serve"):
+        if args.forms == "f32,f64,bf16x3":
+            args.forms = "f32"
+        return serve_bench(args)
     forms = args.forms.split(",")
     w = synth.WORKLOADS[args.workload]
     log("workload %s: n=%d p=%d m=%d t=%d" % (w.name, w.n, w.p, w.m, w.t))

@@ -470,7 +470,9 @@ gwas_status gwas_server_create(gwas_ctx *c, const gwas_server_options *opt, gwas
     s->arena.init(s->arena_mem, budget);
     // ring slots hold the largest slab a request can produce
     const int pmax = std::min(kServeMaxP, c->p);
-    s->ring_bytes = (size_t)round_up((int64_t)s->item_problems + 256 * (int64_t)s->max_traits, 256) * pmax * s->besz;
+    // a slab holds at most max(item_problems, 256 x max_traits) problems (slabs are >= 256 SNPs)
+    s->ring_bytes = (size_t)round_up(std::max<int64_t>(s->item_problems, 256 * (int64_t)s->max_traits), 256) *
+                    pmax * s->besz;
     const int nring = opt->ring_slots ? opt->ring_slots : 2 * s->max_slots;
     for (int k = 0; k < nring; ++k) {
         void *p = nullptr;

@@ -59,7 +59,7 @@ def test_alone_equals_mix_and_matches_oracle(cohort_f32, form):
     from paper_1210_7683_amd import gwas
     d = cohort_f32
     reqs = _requests(1, 7)
-    with gwas.Server(d["c"], form=form, max_slots=4, item_problems=6000) as srv:
+    with gwas.Server(d["c"], form=form, max_slots=4, item_problems=6000, max_traits=64) as srv:
         alone, _ = _run(srv, reqs, together=False)
         mix, res = _run(srv, reqs, together=True)
     for a, b in zip(alone, mix):
@@ -77,7 +77,7 @@ def test_ring_checksums(cohort_f32):
     from paper_1210_7683_amd import gwas
     d = cohort_f32
     reqs = _requests(2, 4)
-    with gwas.Server(d["c"], form="f32", max_slots=3, item_problems=5000) as srv:
+    with gwas.Server(d["c"], form="f32", max_slots=3, item_problems=5000, max_traits=64) as srv:
         ref, _ = _run(srv, reqs, together=False)
         tickets = [srv.submit(y, h2, p) for y, h2, p in reqs]
         res = [srv.wait(tk, timeout=60) for tk in tickets]
@@ -94,15 +94,16 @@ def test_ring_checksums(cohort_f32):
 def test_admission_by_memory_serialises_requests(cohort_f32):
     from paper_1210_7683_amd import gwas
     d = cohort_f32
-    reqs = [(y, h2, 4) for y, h2, _ in _requests(3, 4)]
-    t_max = max(y.shape[0] for y, _, _ in reqs)
-    # a budget that holds one request at a time (the largest needs < 4 MB here)
-    with gwas.Server(d["c"], form="f32", max_slots=8, hbm_budget=4 << 20, item_problems=6000) as srv:
+    rng = np.random.default_rng(3)
+    reqs = [(rng.standard_normal((64, N)), rng.uniform(0.1, 0.9, 64), 4) for _ in range(4)]
+    # each request holds ~0.8 MB (traits, panels, factors, two 256 KB b stages):
+    # a 1.2 MB budget admits one at a time although 8 slots are free
+    with gwas.Server(d["c"], form="f32", max_slots=8, hbm_budget=1200 << 10, item_problems=6000,
+                     max_traits=64) as srv:
         outs, res = _run(srv, reqs, together=True)
     spans = sorted((r["t_admit"], r["t_done"]) for r in res)
     for k in range(len(spans) - 1):
         assert spans[k + 1][0] >= spans[k][1]
-    assert t_max <= 64
 
 
 def test_cancel_and_errors(cohort_f32):
@@ -110,7 +111,7 @@ def test_cancel_and_errors(cohort_f32):
     d = cohort_f32
     y = np.random.default_rng(0).standard_normal((64, N))
     h2 = np.full(64, 0.5)
-    with gwas.Server(d["c"], form="f32", max_slots=1, item_problems=2000) as srv:
+    with gwas.Server(d["c"], form="f32", max_slots=1, item_problems=2000, max_traits=64) as srv:
         first = srv.submit(y, h2, 8)
         queued = srv.submit(y, h2, 8)
         srv.cancel(queued)
@@ -127,7 +128,7 @@ def test_cancel_and_errors(cohort_f32):
         with pytest.raises(gwas.GwasError):
             srv.poll(12345)
     with pytest.raises(gwas.GwasError):
-        gwas.Server(d["c"], form="f64")          # form not resident
-    with gwas.Server(d["c"], form="f32", hbm_budget=1 << 16) as small:
+        gwas.Server(d["c"], form="f64", item_problems=2000, max_traits=64)   # form not resident
+    with gwas.Server(d["c"], form="f32", hbm_budget=1 << 16, item_problems=2000, max_traits=64) as small:
         with pytest.raises(gwas.GwasError):       # can never fit the budget
             small.submit(y, h2, 4)
