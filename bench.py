@@ -152,7 +152,8 @@ def serve_bench(args):
     torch.cuda.synchronize()
     del xr_d
     srv = gwas.Server(cohort, form=form, max_slots=args.slots, max_traits=512,
-                      host_threads=min(16, os.cpu_count() or 1))
+                      host_threads=min(16, os.cpu_count() or 1), ring_slots=args.ring_slots,
+                      skip_checksum=args.skip_checksum, grid_wgs=args.grid_wgs)
     start = gwas.clock() + 0.2
     tickets = []
     for r in reqs:
@@ -161,6 +162,7 @@ def serve_bench(args):
             time.sleep(delay)
         tickets.append(srv.submit(r.y, r.h2, r.p))
     res = [srv.wait(tk, timeout=600) for tk in tickets]
+    sst = srv.stats()
     srv.close()
     cohort.close()
     meas = list(range(args.warmup_requests, len(reqs)))
@@ -182,6 +184,7 @@ def serve_bench(args):
         "latency_max_s": float(lat.max()), "queue_wait_p99_s": float(np.percentile(qwait, 99)),
         "mean_traits": float(np.mean([reqs[k].y.shape[0] for k in meas])),
         "d2h_gbps": bytes_b / span / 1e9, "window_s": span, "all_done": ok,
+        "server": sst, "checksummed": not args.skip_checksum,
     }
     log("serving at %.1f req/s: p50 %.3f s, p99 %.3f s, %.3e GLS/s, b to host %.1f GB/s" %
         (args.rate, line["latency_p50_s"], line["latency_p99_s"], line["value"], line["d2h_gbps"]))
@@ -202,6 +205,9 @@ def main():
     ap.add_argument("--requests", type=int, default=200, help="serving: measured requests")
     ap.add_argument("--warmup-requests", type=int, default=20)
     ap.add_argument("--slots", type=int, default=8, help="serving: requests in flight")
+    ap.add_argument("--ring-slots", type=int, default=0, help="serving: pinned ring slots (0: library default)")
+    ap.add_argument("--skip-checksum", action="store_true", help="serving: do not checksum ring slabs")
+    ap.add_argument("--grid-wgs", type=int, default=0, help="serving: persistent workgroups (0: one per CU)")
     ap.add_argument("--profile-pass", action="store_true",
                     help="one step of the headline form plus a plain 1 GiB device copy (for counter "
                          "calibration), no timing output; meant to run under rocprofv3")

@@ -232,15 +232,16 @@ const char *gwas_last_error(void);
  *
  * A server owns a scheduler thread and a consumer thread. Submitted requests
  * wait in FIFO order until a slot is free and their device memory (rotated
- * traits, panels, factors, two b staging buffers) fits in the server's HBM
+ * traits, panels, factors, three b staging buffers) fits in the server's HBM
  * budget; they are then admitted, their traits rotated and prepared, and
  * their SNP range is cut into work items (slabs). Every scheduling round
  * takes the next slab of each admitted request and runs all of them in one
  * launch, whatever their trait count and covariate count; requests that
  * arrive meanwhile join the next round. Each slab's b is copied to the host
  * on a second stream: into the request's own buffer when it gave one, else
- * through a ring of pinned host slots where it is checksummed (the checksum
- * of gwas_solve_stream) and passed to the request's callback, if any.
+ * through a ring of pinned host slots where a worker thread checksums it (the
+ * checksum of gwas_solve_stream) and passes it to the request's callback, if
+ * any (callbacks of one request may run concurrently, in any slab order).
  * A request's results do not depend on what else is in flight: every problem
  * is computed by the same tile code in the same order, alone or in a mix.
  * Requests use covariate-count prefixes of the cohort's covariates: a request
@@ -255,9 +256,25 @@ typedef struct gwas_server_options {
     int32_t item_problems; /* target problems (SNPs x traits) per work item; 0: 4194304    */
     int32_t max_traits;  /* largest request trait count accepted; 0: 1024                  */
     int32_t ring_slots;  /* pinned host ring slots; 0: 2 x max_slots                       */
-    int32_t host_threads;/* checksum threads per slab; 0: 8                               */
-    int32_t reserved[6];
+    int32_t host_threads;/* checksum worker threads (one ring slab each at a time); 0: 8    */
+    int32_t skip_checksum; /* nonzero: ring slabs are handed to the callback unchecksummed */
+    int32_t grid_wgs;    /* persistent workgroups per launch; 0: one per compute unit, which
+                            leaves room on every unit for the device->host copy kernels  */
+    int32_t reserved[4];
 } gwas_server_options;
+
+typedef struct gwas_server_stats_t {
+    int64_t rounds;          /* grouped launches                                          */
+    int64_t items;           /* work items (slabs) launched                               */
+    int64_t ring_stalls;     /* items deferred because no pinned ring slot was free        */
+    int64_t stage_stalls;    /* items deferred because the request's staging was busy      */
+    int64_t bytes_d2h;       /* b bytes copied to the host                                 */
+    double checksum_s;       /* summed checksum time of the workers                       */
+    double busy_s;           /* wall time with at least one request admitted              */
+    double issue_s;          /* host time the scheduler spent enqueueing launches and copies */
+    double kernel_s;         /* device time of the grouped launches                        */
+    int64_t reserved[6];
+} gwas_server_stats_t;
 
 typedef struct gwas_request {
     int32_t t;           /* traits, 1 .. max_traits                                       */
@@ -316,6 +333,9 @@ gwas_status gwas_server_wait(gwas_server *srv, uint64_t ticket, double timeout_s
 /* Cancel a request: a queued one is dropped, a running one stops issuing
  * slabs and completes as CANCELLED once its slabs in flight have landed. */
 gwas_status gwas_server_cancel(gwas_server *srv, uint64_t ticket);
+
+/* Counters of the server (non-blocking). */
+gwas_status gwas_server_stats(gwas_server *srv, gwas_server_stats_t *out);
 
 /* Cancel what is queued, finish what is running, stop the threads, free. */
 gwas_status gwas_server_destroy(gwas_server *srv);

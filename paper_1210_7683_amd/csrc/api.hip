@@ -439,6 +439,9 @@ gwas_status gwas_solve_stream(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, c
             if (e != hipSuccess)
                 return fail(GWAS_ENOMEM, "pinned ring slot (%zu bytes): %s", c->ring_bytes, hipGetErrorString(e));
             HIP_TRY(hipEventCreateWithFlags(&c->ring_ev[r], hipEventDisableTiming));
+            void *pd = nullptr;
+            HIP_TRY(hipHostGetDevicePointer(&pd, c->ring[r], 0));
+            c->ring_dev.push_back(pd);
         }
     }
 
@@ -479,7 +482,9 @@ gwas_status gwas_solve_stream(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, c
             HIP_TRY(hipEventRecord(c->ev_done[dslot], s));
             HIP_TRY(hipStreamWaitEvent(c->side, c->ev_done[dslot], 0));
             const size_t bytes = (size_t)cnt * jb * p * besz;
-            HIP_TRY(hipMemcpyAsync(c->ring[rslot], c->bstage[dslot], bytes, hipMemcpyDeviceToHost, c->side));
+            // the library's copy kernel moves the slab into the pinned slot (its rate does
+            // not depend on which engine the runtime would pick for a copy)
+            HIP_TRY(launch_copy_to_host(c->ring_dev[rslot], c->bstage[dslot], (int64_t)bytes, 64, c->side));
             HIP_TRY(hipEventRecord(c->ring_ev[rslot], c->side));
             HIP_TRY(hipEventRecord(c->ev_free[dslot], c->side));
             c->bytes_d2h += (int64_t)bytes;

@@ -41,9 +41,16 @@ inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 // Position-weighted checksum of 32-bit words (gwas_checksum), over [k0, k1).
 inline uint64_t checksum_range(const uint32_t *w, int64_t k0, int64_t k1) {
-    uint64_t s = 0;
-    for (int64_t k = k0; k < k1; ++k) s += (uint64_t)(k + 1) * (uint64_t)w[k];
-    return s;
+    uint64_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;   // four independent chains
+    int64_t k = k0;
+    for (; k + 3 < k1; k += 4) {
+        s0 += (uint64_t)(k + 1) * (uint64_t)w[k];
+        s1 += (uint64_t)(k + 2) * (uint64_t)w[k + 1];
+        s2 += (uint64_t)(k + 3) * (uint64_t)w[k + 2];
+        s3 += (uint64_t)(k + 4) * (uint64_t)w[k + 3];
+    }
+    for (; k < k1; ++k) s0 += (uint64_t)(k + 1) * (uint64_t)w[k];
+    return s0 + s1 + s2 + s3;
 }
 
 inline uint64_t checksum_parallel(const void *p, int64_t bytes, int threads) {
@@ -105,6 +112,7 @@ struct gwas_ctx {
     // streamed sink: pinned host ring
     int ring_slots = 4, host_threads = 8;
     std::vector<void *> ring;
+    std::vector<void *> ring_dev;   // device-side addresses of the ring slots
     size_t ring_bytes = 0;
     std::vector<hipEvent_t> ring_ev;
 

@@ -94,6 +94,10 @@ struct FusedArgs {
     int f32_flush;
 };
 hipError_t launch_fused(int form, const FusedArgs &a, hipStream_t s);
+
+// Copy `bytes` (a multiple of 4; 16-byte aligned pointers) from device memory
+// to pinned host memory, given the host buffer's device-side address.
+hipError_t launch_copy_to_host(void *dst_dev_view, const void *src, int64_t bytes, int grid, hipStream_t s);
 hipError_t launch_fused_f64(const FusedArgs &a, hipStream_t s);
 hipError_t launch_fused_f32(const FusedArgs &a, hipStream_t s);
 hipError_t launch_fused_bf16(const FusedArgs &a, hipStream_t s);

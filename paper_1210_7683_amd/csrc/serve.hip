@@ -16,7 +16,7 @@ namespace {
 template <int FORM, bool FLUSH>
 struct ServeTile;
 template <> struct ServeTile<GWAS_FORM_F64, false> { using type = Tile<4, 1, 1, 1, 128, 1>; };
-template <> struct ServeTile<GWAS_FORM_F32, true> { using type = Tile<2, 2, 2, 1, 128, 0>; };
+template <> struct ServeTile<GWAS_FORM_F32, true> { using type = Tile<4, 1, 1, 1, 128, 0>; };
 template <> struct ServeTile<GWAS_FORM_F32, false> { using type = Tile<2, 2, 2, 2, 128, 0>; };
 template <> struct ServeTile<GWAS_FORM_BF16X3, false> { using type = Tile<4, 1, 1, 1, 64, 0>; };
 

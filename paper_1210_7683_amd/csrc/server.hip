@@ -19,6 +19,13 @@ using namespace gw;
 
 namespace {
 
+// Device b staging buffers per admitted request: a slab can be computed while
+// the previous ones are still on their way to the host.
+constexpr int kStages = 3;
+// Workgroups of a ring copy (a copy kernel streams b at the host link's rate
+// with a fraction of the chip).
+constexpr int kCopyGrid = 64;
+
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -79,11 +86,11 @@ struct Req {
     size_t off = 0, bytes = 0;
     double *d_y = nullptr, *d_yt = nullptr, *d_h2 = nullptr, *d_fac = nullptr;
     void *d_panels = nullptr;
-    void *d_stage[2] = {nullptr, nullptr};
+    void *d_stage[kStages] = {};
     size_t stage_bytes = 0;
     int64_t slab = 0, n_slabs = 0, next_slab = 0, in_flight = 0;
     int slot = -1;        // admission slot (owns a pinned staging buffer for Y and h2)
-    bool stage_busy[2] = {false, false};
+    bool stage_busy[kStages] = {};
     bool cancel = false;
     uint64_t checksum = 0;
 };
@@ -92,6 +99,8 @@ struct Copy {
     std::shared_ptr<Req> r;
     int stage = 0, ring = -1;
     hipEvent_t ev = nullptr;
+    hipEvent_t ev_kbeg = nullptr;    // timing: before the round's kernel (first copy of a round only)
+    hipEvent_t ev_kend = nullptr;
     gwas_slab info{};
 };
 
@@ -117,6 +126,7 @@ struct gwas_server {
     hipStream_t s_comp = nullptr, s_copy = nullptr;
     hipEvent_t ev_batch = nullptr;
     std::vector<void *> ring;
+    std::vector<void *> ring_dev;   // device-side addresses of the ring slots
     std::vector<int> ring_free;
     size_t ring_bytes = 0;
     std::vector<hipEvent_t> ev_pool;
@@ -127,17 +137,36 @@ struct gwas_server {
     std::condition_variable cv_sched, cv_cons, cv_done;
     std::deque<std::shared_ptr<Req>> queue;
     std::vector<std::shared_ptr<Req>> active;
-    std::deque<Copy> copies;
+    std::deque<Copy> copies;     // issued device->host copies, in issue order
+    std::deque<Copy> sums;       // landed ring slabs waiting for a checksum worker
+    std::condition_variable cv_sum;
+    std::vector<std::thread> workers;
+    bool stop_workers = false;
     std::unordered_map<uint64_t, std::shared_ptr<Req>> all;
     uint64_t next_ticket = 1;
     bool stop = false, stop_consumer = false, failed = false;
     int fail_status = GWAS_OK;
     std::string fail_msg;
     int rr = 0;
+    bool skip_checksum = false;
+    int64_t n_rounds = 0, n_items = 0, ring_stalls = 0, stage_stalls = 0, bytes_d2h = 0;
+    double checksum_s = 0, busy_s = 0, busy_since = -1, issue_s = 0, kernel_s = 0;
+    std::vector<hipEvent_t> tev_pool;   // timing-enabled events
     std::thread th_sched, th_cons;
 };
 
 namespace {
+
+hipEvent_t tpool_get(gwas_server *s) {   // timing-enabled; caller holds the lock
+    if (!s->tev_pool.empty()) {
+        hipEvent_t e = s->tev_pool.back();
+        s->tev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
 
 hipEvent_t pool_get(gwas_server *s) {   // caller holds the lock
     if (!s->ev_pool.empty()) {
@@ -160,7 +189,7 @@ size_t request_bytes(const gwas_server *s, int t, int p, int64_t slab) {
     auto r = [](size_t v) { return (size_t)round_up((int64_t)v, 256); };
     return r(sizeof(double) * (size_t)t * c->n) + r(sizeof(double) * (size_t)t * c->n_pad) + r(sizeof(double) * t) +
            r(panel_bytes(s->form, p, t, c->n_pad)) + r(sizeof(double) * (size_t)t * fac_stride(p)) +
-           2 * r(stage_bytes_of(s, t, p, slab));
+           kStages * r(stage_bytes_of(s, t, p, slab));
 }
 
 int64_t slab_of(const gwas_server *s, int t, int64_t m) {
@@ -175,6 +204,10 @@ void finish_locked(gwas_server *s, const std::shared_ptr<Req> &r) {
     s->slot_free.push_back(r->slot);
     r->slot = -1;
     s->active.erase(std::find(s->active.begin(), s->active.end(), r));
+    if (s->active.empty() && s->busy_since >= 0) {
+        s->busy_s += r->t_done - s->busy_since;
+        s->busy_since = -1;
+    }
     r->y.clear();
     r->y.shrink_to_fit();
     s->cv_done.notify_all();
@@ -251,10 +284,10 @@ void sched_loop(gwas_server *s) {
             r->d_h2 = (double *)take(sizeof(double) * r->t);
             r->d_panels = take(panel_bytes(s->form, r->p, r->t, c->n_pad));
             r->d_fac = (double *)take(sizeof(double) * (size_t)r->t * fac_stride(r->p));
-            r->d_stage[0] = take(r->stage_bytes);
-            r->d_stage[1] = take(r->stage_bytes);
+            for (int k = 0; k < kStages; ++k) r->d_stage[k] = take(r->stage_bytes);
             r->state = GWAS_REQ_RUNNING;
             r->t_admit = now_s();
+            if (s->active.empty()) s->busy_since = r->t_admit;
             s->active.push_back(r);
             lk.unlock();
             gwas_status st = start_request(s, r.get());
@@ -277,11 +310,17 @@ void sched_loop(gwas_server *s) {
             std::shared_ptr<Req> r = s->active[(s->rr + k) % na];
             if (r->cancel && r->next_slab < r->n_slabs) r->n_slabs = r->next_slab;
             if (r->next_slab >= r->n_slabs) continue;
-            const int st = (int)(r->next_slab & 1);
-            if (r->stage_busy[st]) continue;
+            const int st = (int)(r->next_slab % kStages);
+            if (r->stage_busy[st]) {
+                s->stage_stalls++;
+                continue;
+            }
             int ring = -1;
             if (!r->b_host) {
-                if (s->ring_free.empty()) continue;
+                if (s->ring_free.empty()) {
+                    s->ring_stalls++;
+                    continue;
+                }
                 ring = s->ring_free.back();
                 s->ring_free.pop_back();
             }
@@ -314,6 +353,10 @@ void sched_loop(gwas_server *s) {
             cp.info.form = s->form;
             cp.info.bytes = (int64_t)(cnt * r->t * r->p * s->besz);
             cp.ev = pool_get(s);
+            if (round.empty()) {
+                cp.ev_kbeg = tpool_get(s);
+                cp.ev_kend = tpool_get(s);
+            }
             r->stage_busy[st] = true;
             r->next_slab++;
             r->in_flight++;
@@ -330,8 +373,11 @@ void sched_loop(gwas_server *s) {
             continue;
         }
         lk.unlock();
+        const double t_issue = now_s();
         hipError_t e = hipMemsetAsync(s->d_counter, 0, sizeof(unsigned int), s->s_comp);
+        if (e == hipSuccess && round[0].ev_kbeg) e = hipEventRecord(round[0].ev_kbeg, s->s_comp);
         if (e == hipSuccess) e = launch_serve(s->form, s->flush, bt, s->grid, s->s_comp);
+        if (e == hipSuccess && round[0].ev_kend) e = hipEventRecord(round[0].ev_kend, s->s_comp);
         if (e == hipSuccess) e = hipEventRecord(s->ev_batch, s->s_comp);
         if (e == hipSuccess) e = hipStreamWaitEvent(s->s_copy, s->ev_batch, 0);
         for (Copy &cp : round) {
@@ -340,12 +386,19 @@ void sched_loop(gwas_server *s) {
                                      : (void *)((uint8_t *)cp.r->b_host +
                                                 (size_t)(cp.info.i0 - cp.r->i0) * cp.r->t * cp.r->p * s->besz);
             if (!cp.ev) e = hipErrorOutOfMemory;
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(dst, cp.r->d_stage[cp.stage], (size_t)cp.info.bytes, hipMemcpyDeviceToHost,
-                                   s->s_copy);
+            if (e == hipSuccess) {
+                if (cp.ring >= 0)   // library-owned pinned slot: the copy kernel
+                    e = launch_copy_to_host(s->ring_dev[cp.ring], cp.r->d_stage[cp.stage], cp.info.bytes,
+                                            kCopyGrid, s->s_copy);
+                else                // caller's buffer (may be pageable): the runtime's copy
+                    e = hipMemcpyAsync(dst, cp.r->d_stage[cp.stage], (size_t)cp.info.bytes, hipMemcpyDeviceToHost,
+                                       s->s_copy);
+            }
             if (e == hipSuccess) e = hipEventRecord(cp.ev, s->s_copy);
         }
+        const double dt_issue = now_s() - t_issue;
         lk.lock();
+        s->issue_s += dt_issue;
         if (e != hipSuccess) {
             // nothing of this round can be trusted: wait for the device, then fail everything
             lk.unlock();
@@ -360,11 +413,29 @@ void sched_loop(gwas_server *s) {
             fail_all_locked(s, GWAS_EHIP, std::string("serving launch failed: ") + hipGetErrorString(e));
             continue;
         }
-        for (Copy &cp : round) s->copies.push_back(cp);
+        for (Copy &cp : round) {
+            s->bytes_d2h += cp.info.bytes;
+            s->copies.push_back(cp);
+        }
+        s->n_rounds++;
+        s->n_items += (int64_t)round.size();
         s->cv_cons.notify_one();
     }
 }
 
+// Waits for an event by polling (a dedicated thread: a blocking wait can wake
+// up late, and every retired copy frees a staging buffer and a ring slot).
+void wait_event(hipEvent_t ev) {
+    int spins = 0;
+    while (hipEventQuery(ev) == hipErrorNotReady) {
+        if (++spins < 64) std::this_thread::yield();
+        else std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+}
+
+// Retires device->host copies in issue order: the request's device staging
+// buffer is free as soon as its copy has landed; ring slabs then go to the
+// checksum workers, which release the ring slot.
 void cons_loop(gwas_server *s) {
     hipSetDevice(s->c->dev);
     std::unique_lock<std::mutex> lk(s->mu);
@@ -374,21 +445,52 @@ void cons_loop(gwas_server *s) {
         Copy cp = s->copies.front();
         s->copies.pop_front();
         lk.unlock();
-        hipEventSynchronize(cp.ev);
-        uint64_t cs = 0;
-        if (cp.ring >= 0) {
-            cp.info.b = s->ring[cp.ring];
-            cs = checksum_parallel(cp.info.b, cp.info.bytes, s->host_threads);
-            cp.info.checksum = cs;
-            if (cp.r->fn) cp.r->fn(cp.r->user, &cp.info);
-        }
+        wait_event(cp.ev);
+        float kms = 0.f;
+        if (cp.ev_kbeg) hipEventElapsedTime(&kms, cp.ev_kbeg, cp.ev_kend);
         lk.lock();
+        s->kernel_s += kms * 1e-3;
+        if (cp.ev_kbeg) {
+            s->tev_pool.push_back(cp.ev_kbeg);
+            s->tev_pool.push_back(cp.ev_kend);
+        }
         s->ev_pool.push_back(cp.ev);
-        if (cp.ring >= 0) s->ring_free.push_back(cp.ring);
+        cp.ev = nullptr;
         std::shared_ptr<Req> r = cp.r;
         r->stage_busy[cp.stage] = false;
-        r->in_flight--;
+        if (cp.ring >= 0) {
+            s->sums.push_back(cp);
+            s->cv_sum.notify_one();
+        } else {
+            r->in_flight--;
+            if (r->next_slab >= r->n_slabs && r->in_flight == 0) finish_locked(s, r);
+        }
+        s->cv_sched.notify_one();
+    }
+}
+
+// Checksums landed ring slabs (one slab per worker at a time) and passes them
+// to the request's callback; completes a request with its last slab.
+void sum_loop(gwas_server *s) {
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        while (s->sums.empty() && !s->stop_workers) s->cv_sum.wait(lk);
+        if (s->sums.empty()) break;
+        Copy cp = s->sums.front();
+        s->sums.pop_front();
+        lk.unlock();
+        cp.info.b = s->ring[cp.ring];
+        const double t0 = now_s();
+        const uint64_t cs = s->skip_checksum ? 0 : checksum_range((const uint32_t *)cp.info.b, 0, cp.info.bytes / 4);
+        const double dt = now_s() - t0;
+        cp.info.checksum = cs;
+        if (cp.r->fn) cp.r->fn(cp.r->user, &cp.info);
+        lk.lock();
+        s->checksum_s += dt;
+        s->ring_free.push_back(cp.ring);
+        std::shared_ptr<Req> r = cp.r;
         r->checksum += cs;
+        r->in_flight--;
         if (r->next_slab >= r->n_slabs && r->in_flight == 0) finish_locked(s, r);
         s->cv_sched.notify_one();
     }
@@ -408,6 +510,12 @@ void fill_result(const Req &r, gwas_result *out) {
 
 bool terminal(int st) { return st == GWAS_REQ_DONE || st == GWAS_REQ_CANCELLED || st == GWAS_REQ_FAILED; }
 
+hipError_t create_own_queue_stream(hipStream_t *st, int cus) {
+    std::vector<uint32_t> mask((cus + 31) / 32, 0u);
+    for (int k = 0; k < cus; ++k) mask[k / 32] |= 1u << (k % 32);
+    return hipExtStreamCreateWithCUMask(st, (uint32_t)mask.size(), mask.data());
+}
+
 void free_server(gwas_server *s) {
     if (!s) return;
     if (s->c) hipSetDevice(s->c->dev);
@@ -421,6 +529,7 @@ void free_server(gwas_server *s) {
     for (double *p : s->slot_h2)
         if (p) hipHostFree(p);
     for (hipEvent_t e : s->ev_pool) hipEventDestroy(e);
+    for (hipEvent_t e : s->tev_pool) hipEventDestroy(e);
     if (s->ev_batch) hipEventDestroy(s->ev_batch);
     if (s->s_comp) hipStreamDestroy(s->s_comp);
     if (s->s_copy) hipStreamDestroy(s->s_copy);
@@ -442,7 +551,7 @@ gwas_status gwas_server_create(gwas_ctx *c, const gwas_server_options *opt, gwas
         return fail(GWAS_EINVAL, "form %d is not resident", opt->form);
     if (opt->hbm_budget < 0 || opt->max_slots < 0 || opt->max_slots > kServeMaxItems || opt->item_problems < 0 ||
         opt->max_traits < 0 || opt->ring_slots < 0 || opt->host_threads < 0 || opt->ring_slots > 256 ||
-        opt->host_threads > 256)
+        opt->host_threads > 256 || opt->grid_wgs < 0)
         return fail(GWAS_EINVAL, "option out of range");
     gwas_server *s = new gwas_server();
     s->c = c;
@@ -453,15 +562,19 @@ gwas_status gwas_server_create(gwas_ctx *c, const gwas_server_options *opt, gwas
     s->max_traits = opt->max_traits ? opt->max_traits : 1024;
     s->item_problems = opt->item_problems ? opt->item_problems : (1 << 22);
     s->host_threads = opt->host_threads ? opt->host_threads : 8;
+    s->skip_checksum = opt->skip_checksum != 0;
     const size_t budget = opt->hbm_budget ? (size_t)opt->hbm_budget : ((size_t)8 << 30);
     hipError_t e = hipSetDevice(c->dev);
     int cus = 256;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->dev);
-    s->grid = 2 * cus;
+    s->grid = opt->grid_wgs > 0 ? opt->grid_wgs : cus;
     if (e == hipSuccess) e = hipMalloc(&s->arena_mem, budget);
     if (e == hipSuccess) e = hipMalloc((void **)&s->d_counter, 256);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->s_comp, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->s_copy, hipStreamNonBlocking);
+    // The copy stream must not share a hardware queue with the compute stream, or
+    // the copies (blit kernels) wait behind every launch: streams created with a
+    // compute-unit mask (here: all units) get hardware queues of their own.
+    if (e == hipSuccess) e = create_own_queue_stream(&s->s_comp, cus);
+    if (e == hipSuccess) e = create_own_queue_stream(&s->s_copy, cus);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_batch, hipEventDisableTiming);
     if (e != hipSuccess) {
         free_server(s);
@@ -482,6 +595,13 @@ gwas_status gwas_server_create(gwas_ctx *c, const gwas_server_options *opt, gwas
             return fail(GWAS_ENOMEM, "pinned ring slot (%zu bytes): %s", s->ring_bytes, hipGetErrorString(e));
         }
         s->ring.push_back(p);
+        void *pd = nullptr;
+        e = hipHostGetDevicePointer(&pd, p, 0);
+        if (e != hipSuccess) {
+            free_server(s);
+            return fail(GWAS_EHIP, "ring device address: %s", hipGetErrorString(e));
+        }
+        s->ring_dev.push_back(pd);
         s->ring_free.push_back(k);
     }
     for (int k = 0; k < s->max_slots; ++k) {
@@ -498,6 +618,7 @@ gwas_status gwas_server_create(gwas_ctx *c, const gwas_server_options *opt, gwas
     }
     s->th_sched = std::thread(sched_loop, s);
     s->th_cons = std::thread(cons_loop, s);
+    for (int k = 0; k < s->host_threads; ++k) s->workers.emplace_back(sum_loop, s);
     *out = s;
     return GWAS_OK;
 }
@@ -588,6 +709,23 @@ gwas_status gwas_server_cancel(gwas_server *s, uint64_t ticket) {
     return GWAS_OK;
 }
 
+gwas_status gwas_server_stats(gwas_server *s, gwas_server_stats_t *out) {
+    last_error().clear();
+    if (!s || !out) return fail(GWAS_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    memset(out, 0, sizeof *out);
+    out->rounds = s->n_rounds;
+    out->items = s->n_items;
+    out->ring_stalls = s->ring_stalls;
+    out->stage_stalls = s->stage_stalls;
+    out->bytes_d2h = s->bytes_d2h;
+    out->checksum_s = s->checksum_s;
+    out->busy_s = s->busy_s + (s->busy_since >= 0 ? now_s() - s->busy_since : 0.0);
+    out->issue_s = s->issue_s;
+    out->kernel_s = s->kernel_s;
+    return GWAS_OK;
+}
+
 gwas_status gwas_server_destroy(gwas_server *s) {
     last_error().clear();
     if (!s) return GWAS_OK;
@@ -604,6 +742,13 @@ gwas_status gwas_server_destroy(gwas_server *s) {
         s->cv_cons.notify_one();
     }
     if (s->th_cons.joinable()) s->th_cons.join();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop_workers = true;
+        s->cv_sum.notify_all();
+    }
+    for (auto &th : s->workers)
+        if (th.joinable()) th.join();
     free_server(s);
     return GWAS_OK;
 }

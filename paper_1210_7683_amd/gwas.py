@@ -50,7 +50,16 @@ class ServerOptions(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_int64), ("max_slots", ctypes.c_int32), ("form", ctypes.c_int32),
                 ("item_problems", ctypes.c_int32), ("max_traits", ctypes.c_int32),
                 ("ring_slots", ctypes.c_int32), ("host_threads", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("skip_checksum", ctypes.c_int32), ("grid_wgs", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int64), ("items", ctypes.c_int64), ("ring_stalls", ctypes.c_int64),
+                ("stage_stalls", ctypes.c_int64), ("bytes_d2h", ctypes.c_int64),
+                ("checksum_s", ctypes.c_double), ("busy_s", ctypes.c_double),
+                ("issue_s", ctypes.c_double), ("kernel_s", ctypes.c_double),
+                ("reserved", ctypes.c_int64 * 6)]
 
 
 class Request(ctypes.Structure):
@@ -112,6 +121,8 @@ def load():
     lib.gwas_server_wait.restype = i32
     lib.gwas_server_cancel.argtypes = [vp, ctypes.c_uint64]
     lib.gwas_server_cancel.restype = i32
+    lib.gwas_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.gwas_server_stats.restype = i32
     lib.gwas_server_destroy.argtypes = [vp]
     lib.gwas_server_destroy.restype = i32
     lib.gwas_copy_rotated.argtypes = [vp, i64, i64, i32, vp, i32, vp]
@@ -363,7 +374,8 @@ class Server:
     """
 
     def __init__(self, cohort: "Cohort", form: str = "f32", hbm_budget: int = 0, max_slots: int = 0,
-                 item_problems: int = 0, max_traits: int = 0, ring_slots: int = 0, host_threads: int = 0):
+                 item_problems: int = 0, max_traits: int = 0, ring_slots: int = 0, host_threads: int = 0,
+                 skip_checksum: bool = False, grid_wgs: int = 0):
         lib = load()
         opt = ServerOptions()
         opt.hbm_budget = int(hbm_budget)
@@ -373,6 +385,8 @@ class Server:
         opt.max_traits = int(max_traits)
         opt.ring_slots = int(ring_slots)
         opt.host_threads = int(host_threads)
+        opt.skip_checksum = int(bool(skip_checksum))
+        opt.grid_wgs = int(grid_wgs)
         h = ctypes.c_void_p()
         _check(lib.gwas_server_create(cohort._h, ctypes.byref(opt), ctypes.byref(h)))
         self._h = h
@@ -425,6 +439,11 @@ class Server:
 
     def cancel(self, ticket: int):
         _check(load().gwas_server_cancel(self._h, int(ticket)))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().gwas_server_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_ if k != "reserved"}
 
     def close(self):
         if getattr(self, "_h", None):

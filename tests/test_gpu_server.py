@@ -96,9 +96,9 @@ def test_admission_by_memory_serialises_requests(cohort_f32):
     d = cohort_f32
     rng = np.random.default_rng(3)
     reqs = [(rng.standard_normal((64, N)), rng.uniform(0.1, 0.9, 64), 4) for _ in range(4)]
-    # each request holds ~0.8 MB (traits, panels, factors, two 256 KB b stages):
-    # a 1.2 MB budget admits one at a time although 8 slots are free
-    with gwas.Server(d["c"], form="f32", max_slots=8, hbm_budget=1200 << 10, item_problems=6000,
+    # each request holds ~1.1 MB (traits, panels, factors, three 256 KB b stages):
+    # a 1.6 MB budget admits one at a time although 8 slots are free
+    with gwas.Server(d["c"], form="f32", max_slots=8, hbm_budget=1600 << 10, item_problems=6000,
                      max_traits=64) as srv:
         outs, res = _run(srv, reqs, together=True)
     spans = sorted((r["t_admit"], r["t_done"]) for r in res)
