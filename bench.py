@@ -34,6 +34,20 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0}
 HBM_GBPS = 8000.0
 
 
+def fused_traffic(form: str):
+    """HBM bytes per launch of the headline fused kernel from the committed counter
+    profile, or None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "fused_%s_traffic_paper_m1e5.json" % form)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for s in rec["sources"]:
+        h.update(open(os.path.join(ROOT, s), "rb").read())
+    return rec["traffic_bytes"] if h.hexdigest() == rec["sources_sha256"] else None
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -330,7 +344,7 @@ def main():
         "config": {"workload": w.name, "n": w.n, "p": w.p, "m": w.m, "t": w.t,
                    "form": head, "step": "rotate all SNPs + solve the full grid, b in HBM"},
         "roofline": {"bound": "mfma", "achieved": r["fused_tflops"], "peak": PEAK_TFLOPS[head],
-                     "unit": "TFLOP/s", "frac": r["mfma_frac"], "traffic": None,
+                     "unit": "TFLOP/s", "frac": r["mfma_frac"], "traffic": fused_traffic(head),
                      "kernel": "fused_kernel<%s, p=4>" % head,
                      "flops_per_launch": mult * flops_gls * problems},
         "forms": results,

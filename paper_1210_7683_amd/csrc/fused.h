@@ -384,10 +384,15 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int64_t tile, uin
     if (bad) atomicAdd(a.non_spd, (unsigned long long)bad);
 }
 
+// Workgroups are dispatched round-robin over the chip's 8 XCDs (workgroup b
+// on XCD b mod 8), each with its own L2. With xcd_order, XCD x takes a
+// contiguous eighth of the trait tiles and walks every SNP tile: its trait
+// panels stay in its L2 while the SNP tiles stream through.
 template <int FORM, int P, bool FLUSH, class T>
 __global__ __launch_bounds__((FusedCfg<FORM, P, T>::NT)) void fused_kernel(FusedArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-    fused_tile<FORM, P, FLUSH, T>(a, blockIdx.x, lds);
+    const int ntn = (a.tb + FusedCfg<FORM, P, T>::TN - 1) / FusedCfg<FORM, P, T>::TN;
+    fused_tile<FORM, P, FLUSH, T>(a, xcd_order(blockIdx.x, ntn), lds);
 }
 
 template <int FORM, int P, bool FLUSH, class T = typename DefaultTile<FORM, P, FLUSH>::type>

@@ -23,19 +23,23 @@ struct RotTile {
     static constexpr int EA = TM * KC / NT;   // A elements loaded per thread per chunk
     static constexpr int EB = TN * KC / NT;   // B elements loaded per thread per chunk
     static_assert(FM >= 1 && FN >= 1 && EA >= 1 && EB >= 2 && KC % 8 == 0, "bad rotation tile");
+    static constexpr int LDS = (TM + TN) * LD * 8;
 };
 
-using DefaultRot = RotTile<64, 64, 32, 2, 2>;   // fastest of a tile sweep on MI355X (n = 1000)
+using DefaultRot = RotTile<128, 64, 32, 4, 1>;   // fastest of a tile sweep on MI355X (n = 1000)
 
 template <typename Tin, class R>
 __global__ __launch_bounds__(R::NT) void rotate_kernel(const Tin *__restrict__ X, int64_t rows, int n,
                                                        int64_t ldx, const double *__restrict__ Zr,
                                                        int n_pad, RotOut out) {
     constexpr int TM = R::TM, TN = R::TN, KC = R::KC, LD = R::LD, FM = R::FM, FN = R::FN;
-    __shared__ __attribute__((aligned(16))) double la[TM * LD];
-    __shared__ __attribute__((aligned(16))) double lb[TN * LD];
+    extern __shared__ __attribute__((aligned(16))) double rot_lds[];
+    double *la = rot_lds;
+    double *lb = rot_lds + TM * LD;
     const int ntn = n_pad / TN;
-    const int64_t tile = blockIdx.x;
+    // XCD-aware order: each XCD keeps an eighth of Z's rows in its L2 and
+    // streams the input columns (a bijection of the tiles; results unchanged)
+    const int64_t tile = xcd_order(blockIdx.x, ntn);
     const int tn = (int)(tile % ntn);
     const int64_t tm = tile / ntn;
     const int64_t i_base = tm * TM;
@@ -62,11 +66,26 @@ __global__ __launch_bounds__(R::NT) void rotate_kernel(const Tin *__restrict__ X
         for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
     double va[R::EA], vb[R::EB];
+    // genotype rows are often only 8-byte aligned (n = 1000): uint8 input is
+    // read 8 samples per load when the whole group is in range and aligned
+    const bool vec8 = sizeof(Tin) == 1 && (R::EA % 8) == 0 && (ldx % 8) == 0 && (((uintptr_t)X) % 8) == 0;
     auto gload = [&](int k0) {
+        if (vec8 && gi < rows && k0 + acol + R::EA <= n) {
 #pragma unroll
-        for (int e = 0; e < R::EA; ++e) {
-            const int r = k0 + acol + e;
-            va[e] = (gi < rows && r < n) ? (double)xrow[r] : 0.0;
+            for (int e = 0; e < R::EA; e += 8) {
+                const uint2 v = *(const uint2 *)((const uint8_t *)xrow + k0 + acol + e);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    va[e + q] = (double)((v.x >> (8 * q)) & 0xffu);
+                    va[e + 4 + q] = (double)((v.y >> (8 * q)) & 0xffu);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < R::EA; ++e) {
+                const int r = k0 + acol + e;
+                va[e] = (gi < rows && r < n) ? (double)xrow[r] : 0.0;
+            }
         }
 #pragma unroll
         for (int e = 0; e < R::EB; e += 2) {
@@ -142,17 +161,32 @@ hipError_t launch_rotate_t(const void *X, int dtype, int64_t rows, int n, int64_
     if (n_pad % R::TN) return hipErrorInvalidValue;
     const int64_t tiles = ((rows + R::TM - 1) / R::TM) * (n_pad / R::TN);
     dim3 grid((unsigned)tiles), block(R::NT);
+    if (R::LDS > 65536) {
+        static bool attr_set = false;   // per instantiation
+        if (!attr_set) {
+            hipError_t e = hipFuncSetAttribute((const void *)rotate_kernel<double, R>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, R::LDS);
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute((const void *)rotate_kernel<float, R>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, R::LDS);
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute((const void *)rotate_kernel<uint8_t, R>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, R::LDS);
+            if (e != hipSuccess) return e;
+            attr_set = true;
+        }
+    }
     switch (dtype) {
     case GWAS_DT_F64:
-        hipLaunchKernelGGL((rotate_kernel<double, R>), grid, block, 0, s, (const double *)X, rows, n, ldx, Zrows,
-                           n_pad, out);
+        hipLaunchKernelGGL((rotate_kernel<double, R>), grid, block, R::LDS, s, (const double *)X, rows, n, ldx,
+                           Zrows, n_pad, out);
         break;
     case GWAS_DT_F32:
-        hipLaunchKernelGGL((rotate_kernel<float, R>), grid, block, 0, s, (const float *)X, rows, n, ldx, Zrows,
-                           n_pad, out);
+        hipLaunchKernelGGL((rotate_kernel<float, R>), grid, block, R::LDS, s, (const float *)X, rows, n, ldx,
+                           Zrows, n_pad, out);
         break;
     case GWAS_DT_U8:
-        hipLaunchKernelGGL((rotate_kernel<uint8_t, R>), grid, block, 0, s, (const uint8_t *)X, rows, n, ldx,
+        hipLaunchKernelGGL((rotate_kernel<uint8_t, R>), grid, block, R::LDS, s, (const uint8_t *)X, rows, n, ldx,
                            Zrows, n_pad, out);
         break;
     default:
