@@ -25,6 +25,10 @@
 // 16-byte segment g of row l16 of a 16-row fragment (2 doubles, 4 floats or 8
 // bf16); the same segment->k mapping is used for both operands, so every
 // product pairs equal k.
+//
+// fused_tile is the tile code of the persistent serving loop (register-staged
+// LDS chunks); the direct solve uses the LDS-DMA kernel of fused_dma.h. Both
+// end in fused_epilogue.
 #pragma once
 
 #include <type_traits>
@@ -40,21 +44,6 @@ namespace gw {
 template <int WM_, int WN_, int FM_, int FN_, int CB_, int DB_>
 struct Tile {
     static constexpr int WM = WM_, WN = WN_, FM = FM_, FN = FN_, CB = CB_, DB = DB_;
-};
-
-// Per-form tiles, chosen by timing sweeps on the MI355X at n = 1000, p = 4
-// (m = 1e5, t = 1000); larger p uses smaller tiles to bound the registers held
-// by the p+1 accumulator sets.
-template <int FORM, int P, bool FLUSH>
-struct DefaultTile {
-    using F64T = typename std::conditional<(P <= 4), Tile<4, 1, 1, 2, 128, 1>,
-                 typename std::conditional<(P <= 9), Tile<4, 1, 1, 1, 128, 1>, Tile<2, 2, 1, 1, 64, 0>>::type>::type;
-    using F32T = typename std::conditional<(P <= 9), Tile<2, 2, 2, (FLUSH ? 1 : 2), 128, 0>,
-                                           Tile<2, 2, 1, 1, 64, 0>>::type;
-    using BF16T = typename std::conditional<(P <= 4), Tile<2, 2, 4, 2, 64, 0>,
-                  typename std::conditional<(P <= 9), Tile<4, 1, 1, 1, 64, 0>, Tile<2, 1, 1, 1, 64, 0>>::type>::type;
-    using type = typename std::conditional<FORM == GWAS_FORM_F64, F64T,
-                 typename std::conditional<FORM == GWAS_FORM_F32, F32T, BF16T>::type>::type;
 };
 
 template <int FORM, int P, class T>
@@ -81,6 +70,83 @@ struct FusedCfg {
 template <typename T>
 __device__ __forceinline__ T load16(const uint8_t *p) { return *(const T *)p; }
 
+// FP64 epilogue: Gram assembly and the p x p solve, lane-local. get(q, x, y,
+// r) returns contraction q of register slot r of the wave's MFMA block (x, y).
+template <int FORM, int P, int FM, int FN, class Get>
+__device__ __forceinline__ void fused_epilogue(const FusedArgs &a, Get get, int64_t m_base, int n_base, int wm,
+                                               int wn, int l16, int g) {
+    constexpr int Q = P - 1;
+    constexpr int NTL = Q * (Q + 1) / 2;
+    unsigned bad = 0;
+#pragma unroll
+    for (int x = 0; x < FM; ++x)
+#pragma unroll
+        for (int y = 0; y < FN; ++y) {
+            const int j = n_base + wn * FN * 16 + y * 16 + l16;
+            if (j >= a.tb) continue;
+            const double *F = a.fac + (int64_t)j * a.fac_stride;
+            // small p: the trait's factor is cached in registers; large p reads it
+            // from memory (L1/L2-resident) to keep the epilogue free of spills
+            constexpr bool CACHE = NTL <= 36;
+            double Lc[CACHE ? NTL : 1], z[Q];
+            if constexpr (CACHE) {
+#pragma unroll
+                for (int u = 0; u < NTL; ++u) Lc[u] = F[u];
+            }
+            auto Lf = [&](int u) -> double {
+                if constexpr (CACHE) return Lc[u];
+                else return F[u];
+            };
+#pragma unroll
+            for (int u = 0; u < Q; ++u) z[u] = F[NTL + u];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = m_base + wm * FM * 16 + x * 16 + mfma16_row<FORM == GWAS_FORM_F64>(g, r);
+                if (i >= a.mi) continue;
+                double cq[P + 1];
+#pragma unroll
+                for (int q = 0; q <= P; ++q) cq[q] = get(q, x, y, r);
+                double u[Q];
+                double s = cq[0];
+#pragma unroll
+                for (int aa = 0; aa < Q; ++aa) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int bb = 0; bb <= aa; ++bb) v += Lf(aa * (aa + 1) / 2 + bb) * cq[1 + bb];
+                    u[aa] = v;
+                    s -= v * v;
+                }
+                double num = cq[P];
+#pragma unroll
+                for (int aa = 0; aa < Q; ++aa) num -= u[aa] * z[aa];
+                const bool ok = (s > a.rank_rtol * cq[0]) && isfinite(s) && isfinite(num);
+                const double beta = num / s;
+                double out[P];
+#pragma unroll
+                for (int aa = 0; aa < Q; ++aa) u[aa] = z[aa] - u[aa] * beta;
+#pragma unroll
+                for (int bb = 0; bb < Q; ++bb) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int aa = bb; aa < Q; ++aa) v += Lf(aa * (aa + 1) / 2 + bb) * u[aa];
+                    out[bb] = v;
+                }
+                out[Q] = beta;
+                const int64_t o = (i * a.ldt + j) * P;
+                if constexpr (FORM == GWAS_FORM_F64) {
+                    double *bo = (double *)a.b + o;
+#pragma unroll
+                    for (int v = 0; v < P; ++v) bo[v] = ok ? out[v] : __builtin_nan("");
+                } else {
+                    float *bo = (float *)a.b + o;
+#pragma unroll
+                    for (int v = 0; v < P; ++v) bo[v] = ok ? (float)out[v] : __builtin_nanf("");
+                }
+                bad += ok ? 0u : 1u;
+            }
+        }
+    if (bad) atomicAdd(a.non_spd, (unsigned long long)bad);
+}
 // One TM x TN tile of problems (tile index over the tiles of a, traits fastest),
 // computed by a whole workgroup of C::NT threads with `lds` (C::LDS bytes) as
 // its staging memory. Every thread of the workgroup must call it with the same
@@ -174,6 +240,9 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int64_t tile, uin
                 acc[q][x][y] = acc_t{0, 0, 0, 0};
                 if constexpr (FLUSH) acc64[q][x][y] = d4{0, 0, 0, 0};
             }
+    // FLUSH: the FP32 accumulators hold one 32-sample window (one 128-byte
+    // chunk); after the window's last MFMA they are added to the FP64 sums, and
+    // the next window's first MFMA starts from zero (no register clearing).
     auto fold = [&]() {
         if constexpr (FLUSH) {
 #pragma unroll
@@ -181,21 +250,20 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int64_t tile, uin
 #pragma unroll
                 for (int x = 0; x < FM; ++x)
 #pragma unroll
-                    for (int y = 0; y < FN; ++y) {
+                    for (int y = 0; y < FN; ++y)
 #pragma unroll
                         for (int r = 0; r < 4; ++r) acc64[q][x][y][r] += (double)acc[q][x][y][r];
-                        acc[q][x][y] = acc_t{0, 0, 0, 0};
-                    }
         }
     };
-    int fold_count = 0;
+    static_assert(!FLUSH || (FORM == GWAS_FORM_F32 && CB == 128), "the FP64 fold is per 128-byte FP32 chunk");
 
     const int arow0 = wm * FM * 16 + l16;
     const int brow0 = wn * FN * 16 + l16;
 
     // MFMAs of one 64-byte group of a staged chunk: lane group g reads the
     // 16-byte segment sg of its rows (the same segment of A and B rows).
-    auto compute = [&](const uint8_t *stage, int sg) {
+    auto compute = [&](const uint8_t *stage, int sg, auto first_group) {
+        constexpr bool FRESH = FLUSH && decltype(first_group)::value;   // window starts at zero
         const uint8_t *lA = stage;
         const uint8_t *lB = stage + C::NA * TM * RS;
         const int off = sg * 16;
@@ -235,20 +303,16 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int64_t tile, uin
                     const float b0[4] = {bv[0].x, bv[0].y, bv[0].z, bv[0].w};
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
-                        acc[0][x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[e] * xs[e], b0[e], acc[0][x][y], 0, 0, 0);
+                        acc[0][x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            xs[e] * xs[e], b0[e], (FRESH && e == 0) ? acc_t{0, 0, 0, 0} : acc[0][x][y], 0, 0, 0);
 #pragma unroll
                     for (int q = 1; q < NQ; ++q) {
                         const float bq[4] = {bv[q].x, bv[q].y, bv[q].z, bv[q].w};
 #pragma unroll
                         for (int e = 0; e < 4; ++e)
-                            acc[q][x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[e], bq[e], acc[q][x][y], 0, 0, 0);
+                            acc[q][x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                xs[e], bq[e], (FRESH && e == 0) ? acc_t{0, 0, 0, 0} : acc[q][x][y], 0, 0, 0);
                     }
-                }
-            }
-            if constexpr (FLUSH) {
-                if (++fold_count == a.f32_flush) {
-                    fold();
-                    fold_count = 0;
                 }
             }
         } else {
@@ -282,6 +346,17 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int64_t tile, uin
         }
     };
 
+    // one staged chunk: CB / 64 groups of 64 bytes per row, then the fold
+    auto compute_chunk = [&](const uint8_t *stage) {
+        compute(stage, g, std::true_type{});
+        if constexpr (CB >= 128) compute(stage, 4 + g, std::false_type{});
+        if constexpr (CB >= 256) {
+            compute(stage, 8 + g, std::false_type{});
+            compute(stage, 12 + g, std::false_type{});
+        }
+        fold();
+    };
+
     if constexpr (C::DB) {
         gload(0);
         sstore(lds);
@@ -289,8 +364,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int64_t tile, uin
         for (int c = 0; c < nchunks; ++c) {
             uint8_t *cur = lds + (c & 1) * C::STAGE;
             if (c + 1 < nchunks) gload(c + 1);
-#pragma unroll
-            for (int h = 0; h < CB / 64; ++h) compute(cur, 4 * h + g);
+            compute_chunk(cur);
             if (c + 1 < nchunks) sstore(lds + ((c + 1) & 1) * C::STAGE);
             __syncthreads();
         }
@@ -301,128 +375,15 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int64_t tile, uin
             sstore(lds);
             __syncthreads();
             if (c + 1 < nchunks) gload(c + 1);
-#pragma unroll
-            for (int h = 0; h < CB / 64; ++h) compute(lds, 4 * h + g);
+            compute_chunk(lds);
         }
     }
-    if constexpr (FLUSH) fold();
-
-    // FP64 epilogue: Gram assembly and the p x p solve, lane-local.
-    constexpr int Q = P - 1;
-    constexpr int NTL = Q * (Q + 1) / 2;
-    unsigned bad = 0;
-#pragma unroll
-    for (int x = 0; x < FM; ++x)
-#pragma unroll
-        for (int y = 0; y < FN; ++y) {
-            const int j = n_base + wn * FN * 16 + y * 16 + l16;
-            if (j >= a.tb) continue;
-            const double *F = a.fac + (int64_t)j * a.fac_stride;
-            // small p: the trait's factor is cached in registers; large p reads it
-            // from memory (L1/L2-resident) to keep the epilogue free of spills
-            constexpr bool CACHE = NTL <= 36;
-            double Lc[CACHE ? NTL : 1], z[Q];
-            if constexpr (CACHE) {
-#pragma unroll
-                for (int u = 0; u < NTL; ++u) Lc[u] = F[u];
-            }
-            auto Lf = [&](int u) -> double {
-                if constexpr (CACHE) return Lc[u];
-                else return F[u];
-            };
-#pragma unroll
-            for (int u = 0; u < Q; ++u) z[u] = F[NTL + u];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t i = m_base + wm * FM * 16 + x * 16 + mfma16_row<FORM == GWAS_FORM_F64>(g, r);
-                if (i >= a.mi) continue;
-                double cq[NQ];
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) {
-                    if constexpr (FLUSH) cq[q] = acc64[q][x][y][r];
-                    else cq[q] = (double)acc[q][x][y][r];
-                }
-                double u[Q];
-                double s = cq[0];
-#pragma unroll
-                for (int aa = 0; aa < Q; ++aa) {
-                    double v = 0.0;
-#pragma unroll
-                    for (int bb = 0; bb <= aa; ++bb) v += Lf(aa * (aa + 1) / 2 + bb) * cq[1 + bb];
-                    u[aa] = v;
-                    s -= v * v;
-                }
-                double num = cq[P];
-#pragma unroll
-                for (int aa = 0; aa < Q; ++aa) num -= u[aa] * z[aa];
-                const bool ok = (s > a.rank_rtol * cq[0]) && isfinite(s) && isfinite(num);
-                const double beta = num / s;
-                double out[P];
-#pragma unroll
-                for (int aa = 0; aa < Q; ++aa) u[aa] = z[aa] - u[aa] * beta;
-#pragma unroll
-                for (int bb = 0; bb < Q; ++bb) {
-                    double v = 0.0;
-#pragma unroll
-                    for (int aa = bb; aa < Q; ++aa) v += Lf(aa * (aa + 1) / 2 + bb) * u[aa];
-                    out[bb] = v;
-                }
-                out[Q] = beta;
-                const int64_t o = (i * a.ldt + j) * P;
-                if constexpr (FORM == GWAS_FORM_F64) {
-                    double *bo = (double *)a.b + o;
-#pragma unroll
-                    for (int v = 0; v < P; ++v) bo[v] = ok ? out[v] : __builtin_nan("");
-                } else {
-                    float *bo = (float *)a.b + o;
-#pragma unroll
-                    for (int v = 0; v < P; ++v) bo[v] = ok ? (float)out[v] : __builtin_nanf("");
-                }
-                bad += ok ? 0u : 1u;
-            }
-        }
-    if (bad) atomicAdd(a.non_spd, (unsigned long long)bad);
-}
-
-// Workgroups are dispatched round-robin over the chip's 8 XCDs (workgroup b
-// on XCD b mod 8), each with its own L2. With xcd_order, XCD x takes a
-// contiguous eighth of the trait tiles and walks every SNP tile: its trait
-// panels stay in its L2 while the SNP tiles stream through.
-template <int FORM, int P, bool FLUSH, class T>
-__global__ __launch_bounds__((FusedCfg<FORM, P, T>::NT)) void fused_kernel(FusedArgs a) {
-    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-    const int ntn = (a.tb + FusedCfg<FORM, P, T>::TN - 1) / FusedCfg<FORM, P, T>::TN;
-    fused_tile<FORM, P, FLUSH, T>(a, xcd_order(blockIdx.x, ntn), lds);
-}
-
-template <int FORM, int P, bool FLUSH, class T = typename DefaultTile<FORM, P, FLUSH>::type>
-hipError_t launch_fused_t(const FusedArgs &a, hipStream_t s) {
-    using C = FusedCfg<FORM, P, T>;
-    const int64_t tiles = ((a.mi + C::TM - 1) / C::TM) * ((a.tb + C::TN - 1) / C::TN);
-    if (tiles <= 0) return hipSuccess;
-    if (C::LDS > 65536) {
-        static bool attr_set = false;   // per instantiation
-        if (!attr_set) {
-            hipError_t e = hipFuncSetAttribute((const void *)fused_kernel<FORM, P, FLUSH, T>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS);
-            if (e != hipSuccess) return e;
-            attr_set = true;
-        }
-    }
-    hipLaunchKernelGGL((fused_kernel<FORM, P, FLUSH, T>), dim3((unsigned)tiles), dim3(C::NT), C::LDS, s, a);
-    return hipGetLastError();
-}
-
-template <int FORM, bool FLUSH>
-hipError_t dispatch_p(const FusedArgs &a, hipStream_t s) {
-    switch (a.p) {
-#define GW_CASE(PP) case PP: return launch_fused_t<FORM, PP, FLUSH>(a, s);
-        GW_CASE(2) GW_CASE(3) GW_CASE(4) GW_CASE(5) GW_CASE(6) GW_CASE(7) GW_CASE(8) GW_CASE(9)
-        GW_CASE(10) GW_CASE(11) GW_CASE(12) GW_CASE(13) GW_CASE(14) GW_CASE(15) GW_CASE(16)
-        GW_CASE(17) GW_CASE(18) GW_CASE(19) GW_CASE(20)
-#undef GW_CASE
-    default: return hipErrorInvalidValue;
-    }
+    if constexpr (FLUSH)
+        fused_epilogue<FORM, P, FM, FN>(a, [&](int q, int x, int y, int r) { return acc64[q][x][y][r]; }, m_base,
+                                        n_base, wm, wn, l16, g);
+    else
+        fused_epilogue<FORM, P, FM, FN>(a, [&](int q, int x, int y, int r) { return (double)acc[q][x][y][r]; },
+                                        m_base, n_base, wm, wn, l16, g);
 }
 
 }  // namespace gw

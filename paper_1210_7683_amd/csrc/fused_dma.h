@@ -1,0 +1,312 @@
+// The fused contraction + solve of fused.h with the operands staged by direct
+// global->LDS loads (global_load_lds_dwordx4), for all three forms.
+//
+// LDS layout: the staging buffer is a sequence of 1 KB blocks, each holding one
+// MFMA operand fragment in lane order: lane l of a wave owns bytes
+// 16 l .. 16 l + 15, which are bytes 16 (l / 16) .. + 15 of a 64-byte group of
+// operand row l % 16. One wave-wide 16-byte load fills a block (64 lanes x 16
+// bytes), and the wave that consumes it reads the same 16 bytes per lane back
+// with one ds_read_b128: no staging registers, no LDS bank conflicts, no
+// ds_write. A 64-byte group holds 8 doubles, 16 floats or 32 bf16 per row, so
+// the 16 bytes of lane l are 2, 4 or 8 consecutive samples; lane l supplies
+// them as the k = l / 16 element of 2 (FP64), 4 (FP32) or 1 (BF16, k-block of
+// 8) MFMAs, the same way for both operands, so every product pairs equal k.
+//
+// One stage holds KB groups of every operand row (KB * 64 bytes per row). The
+// loop per stage: wait for the stage's loads, barrier, read the fragments of
+// the whole stage into registers, barrier, issue the next stage's loads into
+// the same LDS (they run under this stage's MFMAs), compute.
+//
+// Split BF16 with SQ (in-register square): only x' hi and lo are staged, and
+// the split of x'^2 is formed from them (x' = hi + lo is exact in FP32; its
+// square is rounded to FP32 and split again), which halves the SNP-side bytes.
+// FP32 with FLUSH: one stage is one 32-sample window (KB = 2); the window's
+// FP32 accumulators are added to FP64 sums after its last MFMA and the next
+// window's first MFMA starts from zero.
+#pragma once
+
+#include "fused.h"
+
+namespace gw {
+
+template <int WM_, int WN_, int FM_, int FN_, int KB_, bool SQ_ = false>
+struct DmaTile {
+    static constexpr int WM = WM_, WN = WN_, FM = FM_, FN = FN_, KB = KB_;
+    static constexpr bool SQ = SQ_;
+};
+
+template <int FORM, int P, class T>
+struct DmaCfg {
+    static constexpr int WM = T::WM, WN = T::WN, FM = T::FM, FN = T::FN, KB = T::KB;
+    static constexpr bool BF = FORM == GWAS_FORM_BF16X3;
+    static constexpr bool SQ = BF && T::SQ;
+    static constexpr int NW = WM * WN;
+    static constexpr int NT = 64 * NW;
+    static constexpr int TM = WM * FM * 16, TN = WN * FN * 16;
+    static constexpr int NQ = P + 1;
+    static constexpr int ESZ = FORM == GWAS_FORM_F64 ? 8 : (FORM == GWAS_FORM_F32 ? 4 : 2);
+    static constexpr int NA = BF ? (SQ ? 2 : 4) : 1;   // staged SNP-side planes
+    static constexpr int NB = BF ? 2 * NQ : NQ;         // staged trait-side planes
+    static constexpr int GA = NA * (TM / 16);           // blocks of one 64-byte group
+    static constexpr int GBK = GA + NB * (TN / 16);
+    static constexpr int BLK = KB * GBK;                // blocks per stage
+    static constexpr int LDS = BLK * 1024;
+    static constexpr int LPW = (BLK + NW - 1) / NW;     // block loads per wave and stage
+    static_assert(KB == 1 || KB == 2, "one or two 64-byte groups per stage");
+    static_assert(LDS <= 160 * 1024, "LDS stage too large");
+};
+
+__device__ __forceinline__ void lds_dma16(const uint8_t *g, uint8_t *l) {
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)g,
+                                     (void __attribute__((address_space(3))) *)l, 16, 0, 0);
+}
+
+// hi/lo split of x'^2 from the split of x' (8 values per lane).
+__device__ __forceinline__ void square_split(const bf16x8 &h, const bf16x8 &l, bf16x8 &sh, bf16x8 &sl) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const float x = (float)h[e] + (float)l[e];
+        const float s = x * x;
+        const __bf16 s_hi = (__bf16)s;
+        sh[e] = s_hi;
+        sl[e] = (__bf16)(s - (float)s_hi);
+    }
+}
+
+template <int FORM>
+struct DmaFrag;
+template <> struct DmaFrag<GWAS_FORM_F64> { using type = double2; using acc = d4; };
+template <> struct DmaFrag<GWAS_FORM_F32> { using type = float4; using acc = f4; };
+template <> struct DmaFrag<GWAS_FORM_BF16X3> { using type = bf16x8; using acc = f4; };
+
+// One workgroup per TM x TN tile. Workgroups are dispatched round-robin over
+// the chip's 8 XCDs (workgroup b on XCD b mod 8), each with its own L2; with
+// xcd_order, XCD x takes a contiguous eighth of the trait tiles and walks every
+// SNP tile, so its trait panels stay in its L2 while the SNP rows stream.
+template <int FORM, int P, bool FLUSH, class T>
+__global__ __launch_bounds__((DmaCfg<FORM, P, T>::NT)) void fused_dma_kernel(FusedArgs a) {
+    using C = DmaCfg<FORM, P, T>;
+    using frag = typename DmaFrag<FORM>::type;
+    using acc_t = typename DmaFrag<FORM>::acc;
+    constexpr int NQ = C::NQ, TM = C::TM, TN = C::TN, FM = C::FM, FN = C::FN, KB = C::KB, NA = C::NA;
+    constexpr bool BF = C::BF;
+    static_assert(!FLUSH || (FORM == GWAS_FORM_F32 && KB == 2), "the FP64 fold is per 32-sample FP32 window");
+    extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
+
+    const int ntn = (a.tb + TN - 1) / TN;
+    const int64_t tile = xcd_order(blockIdx.x, ntn);
+    const int tn = (int)(tile % ntn);
+    const int64_t tm = tile / ntn;
+    const int64_t m_base = tm * TM;
+    const int n_base = tn * TN;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % C::WM, wn = wave / C::WM;
+    const int l16 = lane & 15, g = lane >> 4;
+
+    const int64_t row_bytes = (int64_t)a.n_pad * C::ESZ;
+    const int nstages = (int)(row_bytes / (KB * 64));
+    const uint8_t *A = (const uint8_t *)a.a;
+    const uint8_t *B = (const uint8_t *)a.panels;
+    const int64_t a_plane = a.a_plane_rows * row_bytes;
+    const int64_t b_plane = (int64_t)a.tcap * row_bytes;
+
+    // Per-lane source of every block this wave loads. Block b of a stage is
+    // group kb = b / GBK; within the group, blocks [0, GA) are the SNP planes
+    // (plane-major, 16-row groups), the rest the trait planes. Rows past the
+    // tile's range are clamped into it: they only feed outputs never stored.
+    const uint8_t *src[C::LPW];
+#pragma unroll
+    for (int u = 0; u < C::LPW; ++u) {
+        const int blk = wave + u * C::NW;
+        src[u] = A;
+        if (blk < C::BLK) {
+            const int kb = blk / C::GBK, r = blk % C::GBK;
+            if (r < C::GA) {
+                const int pl = r / (TM / 16), rg = r % (TM / 16);
+                int64_t i = m_base + rg * 16 + l16;
+                if (i >= a.mi) i = a.mi - 1;
+                src[u] = A + pl * a_plane + (a.i0 + i) * row_bytes + kb * 64 + g * 16;
+            } else {
+                const int rb = r - C::GA;
+                const int pl = rb / (TN / 16), cg = rb % (TN / 16);
+                int j = n_base + cg * 16 + l16;
+                if (j >= a.tb) j = a.tb - 1;
+                src[u] = B + pl * b_plane + (int64_t)j * row_bytes + kb * 64 + g * 16;
+            }
+        }
+    }
+    auto issue = [&](int c) {
+#pragma unroll
+        for (int u = 0; u < C::LPW; ++u) {
+            const int blk = wave + u * C::NW;
+            if (blk < C::BLK) lds_dma16(src[u] + (int64_t)c * (KB * 64), lds + blk * 1024);
+        }
+    };
+    auto afrag = [&](int kb, int plane, int x) -> frag {
+        return *(const frag *)(lds + (kb * C::GBK + plane * (TM / 16) + wm * FM + x) * 1024 + lane * 16);
+    };
+    auto bfrag = [&](int kb, int plane, int y) -> frag {
+        return *(const frag *)(lds + (kb * C::GBK + C::GA + plane * (TN / 16) + wn * FN + y) * 1024 + lane * 16);
+    };
+
+    acc_t acc[NQ][FM][FN];
+    d4 acc64[FLUSH ? NQ : 1][FLUSH ? FM : 1][FLUSH ? FN : 1];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int x = 0; x < FM; ++x)
+#pragma unroll
+            for (int y = 0; y < FN; ++y) {
+                acc[q][x][y] = acc_t{0, 0, 0, 0};
+                if constexpr (FLUSH) acc64[q][x][y] = d4{0, 0, 0, 0};
+            }
+
+    issue(0);
+    for (int c = 0; c < nstages; ++c) {
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's loads of stage c landed
+        __syncthreads();                      // ... and every other wave's
+        frag xa[KB][NA][FM], yb[KB][BF ? 2 * NQ : NQ][FN];
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+            for (int pl = 0; pl < NA; ++pl)
+#pragma unroll
+                for (int x = 0; x < FM; ++x) xa[kb][pl][x] = afrag(kb, pl, x);
+#pragma unroll
+            for (int pl = 0; pl < (BF ? 2 * NQ : NQ); ++pl)
+#pragma unroll
+                for (int y = 0; y < FN; ++y) yb[kb][pl][y] = bfrag(kb, pl, y);
+        }
+        __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the fragments are in registers
+        __syncthreads();                      // every wave is done with the stage
+        if (c + 1 < nstages) issue(c + 1);    // the next stage's loads run under the MFMAs
+
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+            const bool fresh = FLUSH && kb == 0;   // an FP32 window starts at zero
+#pragma unroll
+            for (int x = 0; x < FM; ++x) {
+                if constexpr (FORM == GWAS_FORM_F64) {
+                    const double2 xv = xa[kb][0][x];
+#pragma unroll
+                    for (int y = 0; y < FN; ++y) {
+                        acc[0][x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv.x * xv.x, yb[kb][0][y].x, acc[0][x][y], 0, 0, 0);
+                        acc[0][x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv.y * xv.y, yb[kb][0][y].y, acc[0][x][y], 0, 0, 0);
+#pragma unroll
+                        for (int q = 1; q < NQ; ++q) {
+                            acc[q][x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv.x, yb[kb][q][y].x, acc[q][x][y], 0, 0, 0);
+                            acc[q][x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv.y, yb[kb][q][y].y, acc[q][x][y], 0, 0, 0);
+                        }
+                    }
+                } else if constexpr (FORM == GWAS_FORM_F32) {
+                    const float4 xv = xa[kb][0][x];
+                    const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
+#pragma unroll
+                    for (int y = 0; y < FN; ++y) {
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q) {
+                            const float4 bv = yb[kb][q][y];
+                            const float bs[4] = {bv.x, bv.y, bv.z, bv.w};
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const float av = q == 0 ? xs[e] * xs[e] : xs[e];
+                                acc[q][x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                    av, bs[e], (fresh && e == 0) ? acc_t{0, 0, 0, 0} : acc[q][x][y], 0, 0, 0);
+                            }
+                        }
+                    }
+                } else {
+                    const bf16x8 xh = xa[kb][0][x], xl = xa[kb][1][x];
+                    bf16x8 sh, sl;
+                    if constexpr (C::SQ) square_split(xh, xl, sh, sl);
+                    else {
+                        sh = xa[kb][2][x];
+                        sl = xa[kb][3][x];
+                    }
+#pragma unroll
+                    for (int y = 0; y < FN; ++y) {
+                        // q = 0 pairs the split square with the weights; q >= 1 the split value
+                        acc[0][x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sl, yb[kb][0][y], acc[0][x][y], 0, 0, 0);
+                        acc[0][x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sh, yb[kb][1][y], acc[0][x][y], 0, 0, 0);
+                        acc[0][x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sh, yb[kb][0][y], acc[0][x][y], 0, 0, 0);
+#pragma unroll
+                        for (int q = 1; q < NQ; ++q) {
+                            acc[q][x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, yb[kb][2 * q][y], acc[q][x][y], 0, 0, 0);
+                            acc[q][x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, yb[kb][2 * q + 1][y], acc[q][x][y], 0, 0, 0);
+                            acc[q][x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, yb[kb][2 * q][y], acc[q][x][y], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+        }
+        if constexpr (FLUSH) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+#pragma unroll
+                for (int x = 0; x < FM; ++x)
+#pragma unroll
+                    for (int y = 0; y < FN; ++y)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc64[q][x][y][r] += (double)acc[q][x][y][r];
+        }
+    }
+
+    if constexpr (FLUSH)
+        fused_epilogue<FORM, P, FM, FN>(a, [&](int q, int x, int y, int r) { return acc64[q][x][y][r]; }, m_base,
+                                        n_base, wm, wn, l16, g);
+    else
+        fused_epilogue<FORM, P, FM, FN>(a, [&](int q, int x, int y, int r) { return (double)acc[q][x][y][r]; },
+                                        m_base, n_base, wm, wn, l16, g);
+}
+
+template <int FORM, int P, bool FLUSH, class T>
+hipError_t launch_dma_t(const FusedArgs &a, hipStream_t s) {
+    using C = DmaCfg<FORM, P, T>;
+    const int64_t tiles = ((a.mi + C::TM - 1) / C::TM) * ((a.tb + C::TN - 1) / C::TN);
+    if (tiles <= 0) return hipSuccess;
+    if ((a.n_pad * C::ESZ) % (C::KB * 64)) return hipErrorInvalidValue;
+    if (C::LDS > 65536) {
+        static bool attr_set = false;   // per instantiation
+        if (!attr_set) {
+            hipError_t e = hipFuncSetAttribute((const void *)fused_dma_kernel<FORM, P, FLUSH, T>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS);
+            if (e != hipSuccess) return e;
+            attr_set = true;
+        }
+    }
+    hipLaunchKernelGGL((fused_dma_kernel<FORM, P, FLUSH, T>), dim3((unsigned)tiles), dim3(C::NT), C::LDS, s, a);
+    return hipGetLastError();
+}
+
+// Per-form tiles, chosen by timing sweeps on the MI355X at n = 1000, p = 4
+// (m = 1e5, t = 1000): one 16x16 block of problems per wave for FP64 and FP32,
+// 32x32 per wave for split BF16 (more reuse of its larger operands). Larger p
+// narrows the split-BF16 tile, and from p = 10 (FP32: 12) the workgroup drops
+// to 4 waves, one per SIMD, so a wave may hold up to 512 registers of p + 1
+// accumulator sets and fragments without spilling.
+template <int FORM, int P>
+struct DmaDefault {
+    using F64T = typename std::conditional<(P <= 9), DmaTile<4, 2, 1, 1, 1>, DmaTile<4, 1, 1, 1, 1>>::type;
+    using F32T = typename std::conditional<(P <= 11), DmaTile<4, 2, 1, 1, 2>, DmaTile<4, 1, 1, 1, 2>>::type;
+    using BF16T = typename std::conditional<(P <= 4), DmaTile<8, 1, 2, 2, 1, true>,
+                  typename std::conditional<(P <= 9), DmaTile<8, 1, 2, 1, 1, true>,
+                                            DmaTile<4, 1, 1, 1, 1, true>>::type>::type;
+    using type = typename std::conditional<FORM == GWAS_FORM_F64, F64T,
+                 typename std::conditional<FORM == GWAS_FORM_F32, F32T, BF16T>::type>::type;
+};
+
+template <int FORM, bool FLUSH>
+hipError_t dispatch_dma(const FusedArgs &a, hipStream_t s) {
+    switch (a.p) {
+#define GW_CASE(PP) case PP: return launch_dma_t<FORM, PP, FLUSH, typename DmaDefault<FORM, PP>::type>(a, s);
+        GW_CASE(2) GW_CASE(3) GW_CASE(4) GW_CASE(5) GW_CASE(6) GW_CASE(7) GW_CASE(8) GW_CASE(9)
+        GW_CASE(10) GW_CASE(11) GW_CASE(12) GW_CASE(13) GW_CASE(14) GW_CASE(15) GW_CASE(16)
+        GW_CASE(17) GW_CASE(18) GW_CASE(19) GW_CASE(20)
+#undef GW_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace gw
