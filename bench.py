@@ -345,7 +345,7 @@ def main():
                    "form": head, "step": "rotate all SNPs + solve the full grid, b in HBM"},
         "roofline": {"bound": "mfma", "achieved": r["fused_tflops"], "peak": PEAK_TFLOPS[head],
                      "unit": "TFLOP/s", "frac": r["mfma_frac"], "traffic": fused_traffic(head),
-                     "kernel": "fused_kernel<%s, p=4>" % head,
+                     "kernel": "fused_dma_kernel<%s, p=4>" % head,
                      "flops_per_launch": mult * flops_gls * problems},
         "forms": results,
     }
