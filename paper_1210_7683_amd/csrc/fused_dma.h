@@ -29,10 +29,10 @@
 
 namespace gw {
 
-template <int WM_, int WN_, int FM_, int FN_, int KB_, bool SQ_ = false>
+template <int WM_, int WN_, int FM_, int FN_, int KB_, bool SQ_ = false, bool PIPE_ = false>
 struct DmaTile {
     static constexpr int WM = WM_, WN = WN_, FM = FM_, FN = FN_, KB = KB_;
-    static constexpr bool SQ = SQ_;
+    static constexpr bool SQ = SQ_, PIPE = PIPE_;
 };
 
 template <int FORM, int P, class T>
@@ -50,11 +50,79 @@ struct DmaCfg {
     static constexpr int GA = NA * (TM / 16);           // blocks of one 64-byte group
     static constexpr int GBK = GA + NB * (TN / 16);
     static constexpr int BLK = KB * GBK;                // blocks per stage
-    static constexpr int LDS = BLK * 1024;
+    static constexpr bool PIPE = T::PIPE;
+    static constexpr int LDS = (PIPE ? 2 : 1) * BLK * 1024;
     static constexpr int LPW = (BLK + NW - 1) / NW;     // block loads per wave and stage
     static_assert(KB == 1 || KB == 2, "one or two 64-byte groups per stage");
     static_assert(LDS <= 160 * 1024, "LDS stage too large");
+    // the fragments one wave reads per stage, in order: per group kb, the SNP
+    // fragments (plane, x) then the trait fragments (plane, y); offsets are
+    // from the wave's SNP base (stage + lane * 16 + wm * FM KB) or trait base
+    // (stage + lane * 16 + (GA + wn * FN) KB)
+    static constexpr int NBP = BF ? 2 * NQ : NQ;
+    static constexpr int NFA = NA * FM, NFK = NFA + NBP * FN, NF = KB * NFK;
+    static constexpr bool frag_is_b(int i) { return (i % NFK) >= NFA; }
+    static constexpr int frag_off(int i) {
+        return (i % NFK) < NFA
+                   ? ((i / NFK) * GBK + ((i % NFK) / FM) * (TM / 16) + (i % NFK) % FM) * 1024
+                   : ((i / NFK) * GBK + (((i % NFK) - NFA) / FN) * (TN / 16) + ((i % NFK) - NFA) % FN) * 1024;
+    }
+    static_assert(!PIPE || BLK * 1024 <= 65536, "fragment offsets must fit the 16-bit LDS offset field");
 };
+
+typedef int i4v __attribute__((ext_vector_type(4)));
+
+// LDS byte address (offset within the workgroup's LDS) of a shared-memory pointer.
+__device__ __forceinline__ uint32_t lds_addr(const void *p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
+}
+
+// Reads fragments [I0, I0 + N) of a stage (see DmaCfg::frag_off) in blocks of
+// 16/8/4/2/1 ds_read_b128, each block waiting for its own reads before it
+// ends. Written as inline assembly so that the compiler, which cannot tell
+// the two LDS stages apart, does not also wait for the other stage's
+// global->LDS loads in flight.
+#define GW_DSR(k) "ds_read_b128 %" #k ", %[b" #k "] offset:%c[o" #k "]\n"
+#define GW_OUT(k) "=&v"(f[I0 + k])
+#define GW_IN(k) [b##k] "v"(C::frag_is_b(I0 + k) ? bb : ba), [o##k] "i"(C::frag_off(I0 + k))
+template <class C, int I0, int N>
+__device__ __forceinline__ void lds_read_frags(i4v *f, uint32_t ba, uint32_t bb) {
+    if constexpr (N >= 16) {
+        asm volatile(GW_DSR(0) GW_DSR(1) GW_DSR(2) GW_DSR(3) GW_DSR(4) GW_DSR(5) GW_DSR(6) GW_DSR(7) GW_DSR(8)
+                         GW_DSR(9) GW_DSR(10) GW_DSR(11) GW_DSR(12) GW_DSR(13) GW_DSR(14) GW_DSR(15)
+                             "s_waitcnt lgkmcnt(0)"
+                     : GW_OUT(0), GW_OUT(1), GW_OUT(2), GW_OUT(3), GW_OUT(4), GW_OUT(5), GW_OUT(6), GW_OUT(7),
+                       GW_OUT(8), GW_OUT(9), GW_OUT(10), GW_OUT(11), GW_OUT(12), GW_OUT(13), GW_OUT(14), GW_OUT(15)
+                     : GW_IN(0), GW_IN(1), GW_IN(2), GW_IN(3), GW_IN(4), GW_IN(5), GW_IN(6), GW_IN(7), GW_IN(8),
+                       GW_IN(9), GW_IN(10), GW_IN(11), GW_IN(12), GW_IN(13), GW_IN(14), GW_IN(15)
+                     : "memory");
+        lds_read_frags<C, I0 + 16, N - 16>(f, ba, bb);
+    } else if constexpr (N >= 8) {
+        asm volatile(GW_DSR(0) GW_DSR(1) GW_DSR(2) GW_DSR(3) GW_DSR(4) GW_DSR(5) GW_DSR(6) GW_DSR(7)
+                         "s_waitcnt lgkmcnt(0)"
+                     : GW_OUT(0), GW_OUT(1), GW_OUT(2), GW_OUT(3), GW_OUT(4), GW_OUT(5), GW_OUT(6), GW_OUT(7)
+                     : GW_IN(0), GW_IN(1), GW_IN(2), GW_IN(3), GW_IN(4), GW_IN(5), GW_IN(6), GW_IN(7)
+                     : "memory");
+        lds_read_frags<C, I0 + 8, N - 8>(f, ba, bb);
+    } else if constexpr (N >= 4) {
+        asm volatile(GW_DSR(0) GW_DSR(1) GW_DSR(2) GW_DSR(3) "s_waitcnt lgkmcnt(0)"
+                     : GW_OUT(0), GW_OUT(1), GW_OUT(2), GW_OUT(3)
+                     : GW_IN(0), GW_IN(1), GW_IN(2), GW_IN(3)
+                     : "memory");
+        lds_read_frags<C, I0 + 4, N - 4>(f, ba, bb);
+    } else if constexpr (N >= 2) {
+        asm volatile(GW_DSR(0) GW_DSR(1) "s_waitcnt lgkmcnt(0)"
+                     : GW_OUT(0), GW_OUT(1)
+                     : GW_IN(0), GW_IN(1)
+                     : "memory");
+        lds_read_frags<C, I0 + 2, N - 2>(f, ba, bb);
+    } else if constexpr (N == 1) {
+        asm volatile(GW_DSR(0) "s_waitcnt lgkmcnt(0)" : GW_OUT(0) : GW_IN(0) : "memory");
+    }
+}
+#undef GW_DSR
+#undef GW_OUT
+#undef GW_IN
 
 __device__ __forceinline__ void lds_dma16(const uint8_t *g, uint8_t *l) {
     __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)g,
@@ -138,10 +206,11 @@ __global__ __launch_bounds__((DmaCfg<FORM, P, T>::NT)) void fused_dma_kernel(Fus
         }
     }
     auto issue = [&](int c) {
+        uint8_t *stage = lds + (C::PIPE ? (c & 1) * (C::BLK * 1024) : 0);
 #pragma unroll
         for (int u = 0; u < C::LPW; ++u) {
             const int blk = wave + u * C::NW;
-            if (blk < C::BLK) lds_dma16(src[u] + (int64_t)c * (KB * 64), lds + blk * 1024);
+            if (blk < C::BLK) lds_dma16(src[u] + (int64_t)c * (KB * 64), stage + blk * 1024);
         }
     };
     auto afrag = [&](int kb, int plane, int x) -> frag {
@@ -165,23 +234,47 @@ __global__ __launch_bounds__((DmaCfg<FORM, P, T>::NT)) void fused_dma_kernel(Fus
 
     issue(0);
     for (int c = 0; c < nstages; ++c) {
-        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's loads of stage c landed
-        __syncthreads();                      // ... and every other wave's
-        frag xa[KB][NA][FM], yb[KB][BF ? 2 * NQ : NQ][FN];
+        frag xa[KB][NA][FM], yb[KB][C::NBP][FN];
+        if constexpr (C::PIPE) {
+            // two LDS buffers, one barrier per stage: after it, stage c has
+            // landed for every wave and every wave has read stage c - 1, whose
+            // buffer then takes stage c + 1 while stage c is read and computed
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's loads of stage c landed
+            __syncthreads();
+            if (c + 1 < nstages) issue(c + 1);
+            const uint32_t sb = lds_addr(lds) + (c & 1) * (C::BLK * 1024) + lane * 16;
+            i4v fr[C::NF];
+            lds_read_frags<C, 0, C::NF>(fr, sb + wm * FM * 1024, sb + (C::GA + wn * FN) * 1024);
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
+            for (int kb = 0; kb < KB; ++kb) {
 #pragma unroll
-            for (int pl = 0; pl < NA; ++pl)
+                for (int pl = 0; pl < NA; ++pl)
 #pragma unroll
-                for (int x = 0; x < FM; ++x) xa[kb][pl][x] = afrag(kb, pl, x);
+                    for (int x = 0; x < FM; ++x) xa[kb][pl][x] = __builtin_bit_cast(frag, fr[kb * C::NFK + pl * FM + x]);
 #pragma unroll
-            for (int pl = 0; pl < (BF ? 2 * NQ : NQ); ++pl)
+                for (int pl = 0; pl < C::NBP; ++pl)
 #pragma unroll
-                for (int y = 0; y < FN; ++y) yb[kb][pl][y] = bfrag(kb, pl, y);
+                    for (int y = 0; y < FN; ++y)
+                        yb[kb][pl][y] = __builtin_bit_cast(frag, fr[kb * C::NFK + C::NFA + pl * FN + y]);
+            }
+        } else {
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's loads of stage c landed
+            __syncthreads();                      // ... and every other wave's
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+                for (int pl = 0; pl < NA; ++pl)
+#pragma unroll
+                    for (int x = 0; x < FM; ++x) xa[kb][pl][x] = afrag(kb, pl, x);
+#pragma unroll
+                for (int pl = 0; pl < C::NBP; ++pl)
+#pragma unroll
+                    for (int y = 0; y < FN; ++y) yb[kb][pl][y] = bfrag(kb, pl, y);
+            }
+            __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the fragments are in registers
+            __syncthreads();                      // every wave is done with the stage
+            if (c + 1 < nstages) issue(c + 1);    // the next stage's loads run under the MFMAs
         }
-        __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): the fragments are in registers
-        __syncthreads();                      // every wave is done with the stage
-        if (c + 1 < nstages) issue(c + 1);    // the next stage's loads run under the MFMAs
 
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
@@ -282,17 +375,19 @@ hipError_t launch_dma_t(const FusedArgs &a, hipStream_t s) {
 
 // Per-form tiles, chosen by timing sweeps on the MI355X at n = 1000, p = 4
 // (m = 1e5, t = 1000): one 16x16 block of problems per wave for FP64 and FP32,
-// 32x32 per wave for split BF16 (more reuse of its larger operands). Larger p
-// narrows the split-BF16 tile, and from p = 10 (FP32: 12) the workgroup drops
-// to 4 waves, one per SIMD, so a wave may hold up to 512 registers of p + 1
-// accumulator sets and fragments without spilling.
+// 32x32 per wave for split BF16 (more reuse of its larger operands). FP32 and
+// split BF16 run two LDS buffers (PIPE); for FP64 the single buffer with a
+// smaller LDS footprint measured faster. Larger p narrows the split-BF16 tile,
+// and from p = 10 (FP32: 12) the workgroup drops to 4 waves, one per SIMD, so
+// a wave may hold up to 512 registers of p + 1 accumulator sets and fragments.
 template <int FORM, int P>
 struct DmaDefault {
     using F64T = typename std::conditional<(P <= 9), DmaTile<4, 2, 1, 1, 1>, DmaTile<4, 1, 1, 1, 1>>::type;
-    using F32T = typename std::conditional<(P <= 11), DmaTile<4, 2, 1, 1, 2>, DmaTile<4, 1, 1, 1, 2>>::type;
-    using BF16T = typename std::conditional<(P <= 4), DmaTile<8, 1, 2, 2, 1, true>,
-                  typename std::conditional<(P <= 9), DmaTile<8, 1, 2, 1, 1, true>,
-                                            DmaTile<4, 1, 1, 1, 1, true>>::type>::type;
+    using F32T = typename std::conditional<(P <= 11), DmaTile<8, 1, 1, 1, 2, false, true>,
+                                           DmaTile<4, 1, 1, 1, 2, false, true>>::type;
+    using BF16T = typename std::conditional<(P <= 4), DmaTile<8, 1, 2, 2, 1, true, true>,
+                  typename std::conditional<(P <= 9), DmaTile<8, 1, 2, 1, 1, true, true>,
+                                            DmaTile<4, 1, 1, 1, 1, true, true>>::type>::type;
     using type = typename std::conditional<FORM == GWAS_FORM_F64, F64T,
                  typename std::conditional<FORM == GWAS_FORM_F32, F32T, BF16T>::type>::type;
 };
