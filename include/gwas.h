@@ -118,7 +118,7 @@ gwas_status gwas_setup(gwas_ctx **ctx, int32_t n, int32_t p, const double *Z, co
 /*
  * Rotate SNPs [m0, m0 + mb) into the resident store: X'_R = Z^T X_R
  * (Algorithm 5, preloop), as an FP64 MFMA GEMM; the result is kept in every
- * resident form (FP64; rounded to FP32; split to BF16 hi/lo with its square).
+ * resident form (FP64; rounded to FP32; split to BF16 hi/lo).
  *   X_R        n x mb, SNP-major, element type dtype (GWAS_DT_*)
  *   on_device  nonzero: X_R is device memory; zero: host memory (copied in
  *              bounded chunks through a device staging buffer)

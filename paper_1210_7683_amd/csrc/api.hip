@@ -181,7 +181,7 @@ gwas_status gwas_setup(gwas_ctx **out, int32_t n, int32_t p, const double *Z, co
     const size_t plane = (size_t)c->m_rows * np;
     if (forms & GWAS_FORM_BIT(GWAS_FORM_F64)) TRY(dalloc(c, &c->xr64, sizeof(double) * plane));
     if (forms & GWAS_FORM_BIT(GWAS_FORM_F32)) TRY(dalloc(c, &c->xr32, sizeof(float) * plane));
-    if (forms & GWAS_FORM_BIT(GWAS_FORM_BF16X3)) TRY(dalloc(c, &c->xrbf, sizeof(uint16_t) * 4 * plane));
+    if (forms & GWAS_FORM_BIT(GWAS_FORM_BF16X3)) TRY(dalloc(c, &c->xrbf, sizeof(uint16_t) * 2 * plane));
     TRY(dalloc(c, &c->y_in, sizeof(double) * (size_t)c->tcap * n));
     TRY(dalloc(c, &c->yt, sizeof(double) * (size_t)c->tcap * np));
     TRY(dalloc(c, &c->h2, sizeof(double) * (size_t)c->tcap));

@@ -91,7 +91,7 @@ struct gwas_ctx {
     double *xlt = nullptr;   // [p-1][n_pad]
     double *xr64 = nullptr;  // [m_rows][n_pad]
     float *xr32 = nullptr;   // [m_rows][n_pad]
-    uint16_t *xrbf = nullptr;  // 4 planes [m_rows][n_pad]
+    uint16_t *xrbf = nullptr;  // 2 planes (x' hi, lo) [m_rows][n_pad]
 
     double *y_in = nullptr;  // [tcap][n] staging of host traits
     double *yt = nullptr;    // [tcap][n_pad]

@@ -53,7 +53,7 @@ struct FusedCfg {
     static constexpr int TM = WM * FM * 16;
     static constexpr int TN = WN * FN * 16;
     static constexpr int NQ = P + 1;
-    static constexpr int NA = (FORM == GWAS_FORM_BF16X3) ? 4 : 1;        // SNP-side planes
+    static constexpr int NA = (FORM == GWAS_FORM_BF16X3) ? 2 : 1;        // SNP-side planes
     static constexpr int NB = (FORM == GWAS_FORM_BF16X3) ? 2 * NQ : NQ;  // trait-side planes
     static constexpr int ESZ = (FORM == GWAS_FORM_F64) ? 8 : (FORM == GWAS_FORM_F32 ? 4 : 2);
     static constexpr int SPR = CB / 16;          // 16-byte segments per row per chunk
@@ -69,6 +69,19 @@ struct FusedCfg {
 
 template <typename T>
 __device__ __forceinline__ T load16(const uint8_t *p) { return *(const T *)p; }
+
+// Split-BF16 square: the hi/lo split of x'^2 from the split of x' (8 values per
+// lane): x' = hi + lo is exact in FP32, its square is rounded to FP32 and split.
+__device__ __forceinline__ void square_split(const bf16x8 &h, const bf16x8 &l, bf16x8 &sh, bf16x8 &sl) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const float x = (float)h[e] + (float)l[e];
+        const float s = x * x;
+        const __bf16 s_hi = (__bf16)s;
+        sh[e] = s_hi;
+        sl[e] = (__bf16)(s - (float)s_hi);
+    }
+}
 
 // FP64 epilogue: Gram assembly and the p x p solve, lane-local. get(q, x, y,
 // r) returns contraction q of register slot r of the wave's MFMA block (x, y).
@@ -316,11 +329,13 @@ __device__ __forceinline__ void fused_tile(const FusedArgs &a, int64_t tile, uin
                 }
             }
         } else {
-            bf16x8 av[4][FM];
+            bf16x8 av[4][FM];   // x' hi, lo (staged), x'^2 hi, lo (formed here)
 #pragma unroll
-            for (int pl = 0; pl < 4; ++pl)
+            for (int pl = 0; pl < 2; ++pl)
 #pragma unroll
                 for (int x = 0; x < FM; ++x) av[pl][x] = load16<bf16x8>(lA + (pl * TM + arow0 + x * 16) * RS + off);
+#pragma unroll
+            for (int x = 0; x < FM; ++x) square_split(av[0][x], av[1][x], av[2][x], av[3][x]);
 #pragma unroll
             for (int y = 0; y < FN; ++y) {
                 bf16x8 bh[NQ], bl[NQ];

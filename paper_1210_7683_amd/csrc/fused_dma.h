@@ -17,9 +17,8 @@
 // the whole stage into registers, barrier, issue the next stage's loads into
 // the same LDS (they run under this stage's MFMAs), compute.
 //
-// Split BF16 with SQ (in-register square): only x' hi and lo are staged, and
-// the split of x'^2 is formed from them (x' = hi + lo is exact in FP32; its
-// square is rounded to FP32 and split again), which halves the SNP-side bytes.
+// Split BF16: only x' hi and lo are staged; the split of x'^2 is formed from
+// them in registers (square_split), which halves the SNP-side bytes.
 // FP32 with FLUSH: one stage is one 32-sample window (KB = 2); the window's
 // FP32 accumulators are added to FP64 sums after its last MFMA and the next
 // window's first MFMA starts from zero.
@@ -29,23 +28,22 @@
 
 namespace gw {
 
-template <int WM_, int WN_, int FM_, int FN_, int KB_, bool SQ_ = false, bool PIPE_ = false>
+template <int WM_, int WN_, int FM_, int FN_, int KB_, bool PIPE_ = false>
 struct DmaTile {
     static constexpr int WM = WM_, WN = WN_, FM = FM_, FN = FN_, KB = KB_;
-    static constexpr bool SQ = SQ_, PIPE = PIPE_;
+    static constexpr bool PIPE = PIPE_;
 };
 
 template <int FORM, int P, class T>
 struct DmaCfg {
     static constexpr int WM = T::WM, WN = T::WN, FM = T::FM, FN = T::FN, KB = T::KB;
     static constexpr bool BF = FORM == GWAS_FORM_BF16X3;
-    static constexpr bool SQ = BF && T::SQ;
     static constexpr int NW = WM * WN;
     static constexpr int NT = 64 * NW;
     static constexpr int TM = WM * FM * 16, TN = WN * FN * 16;
     static constexpr int NQ = P + 1;
     static constexpr int ESZ = FORM == GWAS_FORM_F64 ? 8 : (FORM == GWAS_FORM_F32 ? 4 : 2);
-    static constexpr int NA = BF ? (SQ ? 2 : 4) : 1;   // staged SNP-side planes
+    static constexpr int NA = BF ? 2 : 1;               // staged SNP-side planes
     static constexpr int NB = BF ? 2 * NQ : NQ;         // staged trait-side planes
     static constexpr int GA = NA * (TM / 16);           // blocks of one 64-byte group
     static constexpr int GBK = GA + NB * (TN / 16);
@@ -127,18 +125,6 @@ __device__ __forceinline__ void lds_read_frags(i4v *f, uint32_t ba, uint32_t bb)
 __device__ __forceinline__ void lds_dma16(const uint8_t *g, uint8_t *l) {
     __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)g,
                                      (void __attribute__((address_space(3))) *)l, 16, 0, 0);
-}
-
-// hi/lo split of x'^2 from the split of x' (8 values per lane).
-__device__ __forceinline__ void square_split(const bf16x8 &h, const bf16x8 &l, bf16x8 &sh, bf16x8 &sl) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const float x = (float)h[e] + (float)l[e];
-        const float s = x * x;
-        const __bf16 s_hi = (__bf16)s;
-        sh[e] = s_hi;
-        sl[e] = (__bf16)(s - (float)s_hi);
-    }
 }
 
 template <int FORM>
@@ -313,11 +299,7 @@ __global__ __launch_bounds__((DmaCfg<FORM, P, T>::NT)) void fused_dma_kernel(Fus
                 } else {
                     const bf16x8 xh = xa[kb][0][x], xl = xa[kb][1][x];
                     bf16x8 sh, sl;
-                    if constexpr (C::SQ) square_split(xh, xl, sh, sl);
-                    else {
-                        sh = xa[kb][2][x];
-                        sl = xa[kb][3][x];
-                    }
+                    square_split(xh, xl, sh, sl);
 #pragma unroll
                     for (int y = 0; y < FN; ++y) {
                         // q = 0 pairs the split square with the weights; q >= 1 the split value
@@ -383,11 +365,11 @@ hipError_t launch_dma_t(const FusedArgs &a, hipStream_t s) {
 template <int FORM, int P>
 struct DmaDefault {
     using F64T = typename std::conditional<(P <= 9), DmaTile<4, 2, 1, 1, 1>, DmaTile<4, 1, 1, 1, 1>>::type;
-    using F32T = typename std::conditional<(P <= 11), DmaTile<8, 1, 1, 1, 2, false, true>,
-                                           DmaTile<4, 1, 1, 1, 2, false, true>>::type;
-    using BF16T = typename std::conditional<(P <= 4), DmaTile<8, 1, 2, 2, 1, true, true>,
-                  typename std::conditional<(P <= 9), DmaTile<8, 1, 2, 1, 1, true, true>,
-                                            DmaTile<4, 1, 1, 1, 1, true, true>>::type>::type;
+    using F32T = typename std::conditional<(P <= 11), DmaTile<8, 1, 1, 1, 2, true>,
+                                           DmaTile<4, 1, 1, 1, 2, true>>::type;
+    using BF16T = typename std::conditional<(P <= 4), DmaTile<8, 1, 2, 2, 1, true>,
+                  typename std::conditional<(P <= 9), DmaTile<8, 1, 2, 1, 1, true>,
+                                            DmaTile<4, 1, 1, 1, 1, true>>::type>::type;
     using type = typename std::conditional<FORM == GWAS_FORM_F64, F64T,
                  typename std::conditional<FORM == GWAS_FORM_F32, F32T, BF16T>::type>::type;
 };

@@ -57,7 +57,7 @@ __device__ __forceinline__ void bf16_split(float x, uint16_t &hi, uint16_t &lo) 
 struct RotOut {
     double *f64;      // [rows][ld]
     float *f32;       // [rows][ld]
-    uint16_t *bf;     // 4 planes, each [plane_rows][ld]: x hi, x lo, x^2 hi, x^2 lo
+    uint16_t *bf;     // 2 planes, each [plane_rows][ld]: x hi, x lo
     int64_t plane_rows;
     int64_t row0;     // first output row
     int ld;           // n_pad
@@ -88,7 +88,7 @@ inline int fac_stride(int p) {
 // Fused contraction + solve.
 struct FusedArgs {
     const void *a;          // resident rotated SNP planes (form layout), rows of n_pad
-    int64_t a_plane_rows;   // rows per plane (bf16 form has 4 planes)
+    int64_t a_plane_rows;   // rows per plane (the bf16 form has 2 planes)
     int64_t i0, mi;         // SNP range
     const void *panels;     // trait panels, plane stride tcap rows
     int tcap;

@@ -5,8 +5,8 @@
 // (v_mfma_f64_16x16x4f64) over LDS-staged K chunks.
 //
 // The rotated rows are written in every resident form at once: FP64, rounded
-// to FP32, and split to BF16 hi/lo together with the split of the square x'^2
-// (the square is taken in FP64 and rounded to FP32 before the split).
+// to FP32, and split to BF16 hi/lo (the split of x'^2 is formed by the fused
+// kernels from hi/lo).
 #include "gwas_internal.h"
 
 namespace gw {
@@ -145,9 +145,6 @@ __global__ __launch_bounds__(R::NT) void rotate_kernel(const Tin *__restrict__ X
                     const int64_t ps = out.plane_rows * out.ld;
                     out.bf[o] = h;
                     out.bf[ps + o] = l;
-                    bf16_split((float)(v * v), h, l);
-                    out.bf[2 * ps + o] = h;
-                    out.bf[3 * ps + o] = l;
                 }
             }
 }
