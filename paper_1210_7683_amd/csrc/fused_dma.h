@@ -25,6 +25,7 @@
 #pragma once
 
 #include "fused.h"
+#include "lds_dma.h"
 
 namespace gw {
 
@@ -68,64 +69,6 @@ struct DmaCfg {
     static_assert(!PIPE || BLK * 1024 <= 65536, "fragment offsets must fit the 16-bit LDS offset field");
 };
 
-typedef int i4v __attribute__((ext_vector_type(4)));
-
-// LDS byte address (offset within the workgroup's LDS) of a shared-memory pointer.
-__device__ __forceinline__ uint32_t lds_addr(const void *p) {
-    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
-}
-
-// Reads fragments [I0, I0 + N) of a stage (see DmaCfg::frag_off) in blocks of
-// 16/8/4/2/1 ds_read_b128, each block waiting for its own reads before it
-// ends. Written as inline assembly so that the compiler, which cannot tell
-// the two LDS stages apart, does not also wait for the other stage's
-// global->LDS loads in flight.
-#define GW_DSR(k) "ds_read_b128 %" #k ", %[b" #k "] offset:%c[o" #k "]\n"
-#define GW_OUT(k) "=&v"(f[I0 + k])
-#define GW_IN(k) [b##k] "v"(C::frag_is_b(I0 + k) ? bb : ba), [o##k] "i"(C::frag_off(I0 + k))
-template <class C, int I0, int N>
-__device__ __forceinline__ void lds_read_frags(i4v *f, uint32_t ba, uint32_t bb) {
-    if constexpr (N >= 16) {
-        asm volatile(GW_DSR(0) GW_DSR(1) GW_DSR(2) GW_DSR(3) GW_DSR(4) GW_DSR(5) GW_DSR(6) GW_DSR(7) GW_DSR(8)
-                         GW_DSR(9) GW_DSR(10) GW_DSR(11) GW_DSR(12) GW_DSR(13) GW_DSR(14) GW_DSR(15)
-                             "s_waitcnt lgkmcnt(0)"
-                     : GW_OUT(0), GW_OUT(1), GW_OUT(2), GW_OUT(3), GW_OUT(4), GW_OUT(5), GW_OUT(6), GW_OUT(7),
-                       GW_OUT(8), GW_OUT(9), GW_OUT(10), GW_OUT(11), GW_OUT(12), GW_OUT(13), GW_OUT(14), GW_OUT(15)
-                     : GW_IN(0), GW_IN(1), GW_IN(2), GW_IN(3), GW_IN(4), GW_IN(5), GW_IN(6), GW_IN(7), GW_IN(8),
-                       GW_IN(9), GW_IN(10), GW_IN(11), GW_IN(12), GW_IN(13), GW_IN(14), GW_IN(15)
-                     : "memory");
-        lds_read_frags<C, I0 + 16, N - 16>(f, ba, bb);
-    } else if constexpr (N >= 8) {
-        asm volatile(GW_DSR(0) GW_DSR(1) GW_DSR(2) GW_DSR(3) GW_DSR(4) GW_DSR(5) GW_DSR(6) GW_DSR(7)
-                         "s_waitcnt lgkmcnt(0)"
-                     : GW_OUT(0), GW_OUT(1), GW_OUT(2), GW_OUT(3), GW_OUT(4), GW_OUT(5), GW_OUT(6), GW_OUT(7)
-                     : GW_IN(0), GW_IN(1), GW_IN(2), GW_IN(3), GW_IN(4), GW_IN(5), GW_IN(6), GW_IN(7)
-                     : "memory");
-        lds_read_frags<C, I0 + 8, N - 8>(f, ba, bb);
-    } else if constexpr (N >= 4) {
-        asm volatile(GW_DSR(0) GW_DSR(1) GW_DSR(2) GW_DSR(3) "s_waitcnt lgkmcnt(0)"
-                     : GW_OUT(0), GW_OUT(1), GW_OUT(2), GW_OUT(3)
-                     : GW_IN(0), GW_IN(1), GW_IN(2), GW_IN(3)
-                     : "memory");
-        lds_read_frags<C, I0 + 4, N - 4>(f, ba, bb);
-    } else if constexpr (N >= 2) {
-        asm volatile(GW_DSR(0) GW_DSR(1) "s_waitcnt lgkmcnt(0)"
-                     : GW_OUT(0), GW_OUT(1)
-                     : GW_IN(0), GW_IN(1)
-                     : "memory");
-        lds_read_frags<C, I0 + 2, N - 2>(f, ba, bb);
-    } else if constexpr (N == 1) {
-        asm volatile(GW_DSR(0) "s_waitcnt lgkmcnt(0)" : GW_OUT(0) : GW_IN(0) : "memory");
-    }
-}
-#undef GW_DSR
-#undef GW_OUT
-#undef GW_IN
-
-__device__ __forceinline__ void lds_dma16(const uint8_t *g, uint8_t *l) {
-    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)g,
-                                     (void __attribute__((address_space(3))) *)l, 16, 0, 0);
-}
 
 template <int FORM>
 struct DmaFrag;
@@ -155,7 +98,8 @@ __global__ __launch_bounds__((DmaCfg<FORM, P, T>::NT)) void fused_dma_kernel(Fus
     const int n_base = tn * TN;
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
     const int wm = wave % C::WM, wn = wave / C::WM;
     const int l16 = lane & 15, g = lane >> 4;
 
@@ -166,28 +110,35 @@ __global__ __launch_bounds__((DmaCfg<FORM, P, T>::NT)) void fused_dma_kernel(Fus
     const int64_t a_plane = a.a_plane_rows * row_bytes;
     const int64_t b_plane = (int64_t)a.tcap * row_bytes;
 
-    // Per-lane source of every block this wave loads. Block b of a stage is
-    // group kb = b / GBK; within the group, blocks [0, GA) are the SNP planes
-    // (plane-major, 16-row groups), the rest the trait planes. Rows past the
-    // tile's range are clamped into it: they only feed outputs never stored.
-    const uint8_t *src[C::LPW];
+    // Source of every block this wave loads: a wave-uniform base (plane, tile
+    // origin, group) plus a per-lane 32-bit offset (row within the tile, lane
+    // group), so the loads use scalar base addresses and the stage advance is
+    // scalar arithmetic. Block b of a stage is group kb = b / GBK; within the
+    // group, blocks [0, GA) are the SNP planes (plane-major, 16-row groups), the
+    // rest the trait planes. Rows past the tile's range are clamped into it:
+    // they only feed outputs that are never stored.
+    const uint8_t *sbase[C::LPW];
+    uint32_t voff[C::LPW];
 #pragma unroll
     for (int u = 0; u < C::LPW; ++u) {
         const int blk = wave + u * C::NW;
-        src[u] = A;
+        sbase[u] = A;
+        voff[u] = 0;
         if (blk < C::BLK) {
             const int kb = blk / C::GBK, r = blk % C::GBK;
             if (r < C::GA) {
                 const int pl = r / (TM / 16), rg = r % (TM / 16);
                 int64_t i = m_base + rg * 16 + l16;
                 if (i >= a.mi) i = a.mi - 1;
-                src[u] = A + pl * a_plane + (a.i0 + i) * row_bytes + kb * 64 + g * 16;
+                sbase[u] = A + pl * a_plane + (a.i0 + m_base) * row_bytes + kb * 64;
+                voff[u] = (uint32_t)((i - m_base) * row_bytes) + g * 16;
             } else {
                 const int rb = r - C::GA;
                 const int pl = rb / (TN / 16), cg = rb % (TN / 16);
                 int j = n_base + cg * 16 + l16;
                 if (j >= a.tb) j = a.tb - 1;
-                src[u] = B + pl * b_plane + (int64_t)j * row_bytes + kb * 64 + g * 16;
+                sbase[u] = B + pl * b_plane + (int64_t)n_base * row_bytes + kb * 64;
+                voff[u] = (uint32_t)((j - n_base) * row_bytes) + g * 16;
             }
         }
     }
@@ -196,7 +147,7 @@ __global__ __launch_bounds__((DmaCfg<FORM, P, T>::NT)) void fused_dma_kernel(Fus
 #pragma unroll
         for (int u = 0; u < C::LPW; ++u) {
             const int blk = wave + u * C::NW;
-            if (blk < C::BLK) lds_dma16(src[u] + (int64_t)c * (KB * 64), stage + blk * 1024);
+            if (blk < C::BLK) lds_dma16(sbase[u] + (int64_t)c * (KB * 64) + voff[u], stage + blk * 1024);
         }
     };
     auto afrag = [&](int kb, int plane, int x) -> frag {

@@ -79,6 +79,26 @@ def test_rotate_dtypes_and_device_input(tiny, dtype, torch_cuda):
     c.close()
 
 
+@pytest.mark.parametrize("n,m", [(77, 129), (200, 333), (1000, 300)])
+def test_genotype_rotation_ragged_n_and_rows(n, m, torch_cuda):
+    """uint8 genotypes with n not a multiple of the 64-sample stage (and, for
+    n = 77, rows not 8-byte aligned), rows not a multiple of the SNP tile:
+    every rotated value against the FP64 product, in all three stores."""
+    torch = torch_cuda
+    phi, xl, xr, _, _ = synth.small(n, 3, m, 2, seed=n + m)
+    assert xr.dtype == np.uint8
+    w, z = np.linalg.eigh(phi)
+    from paper_1210_7683_amd import gwas
+    c = gwas.Cohort(z, w, xl, m + 5)
+    c.rotate(5, torch.from_numpy(xr).cuda())
+    torch.cuda.synchronize()
+    ref = xr.astype(np.float64) @ z
+    got = c.copy_rotated(5, m, "f64")
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert np.array_equal(c.copy_rotated(5, m, "f32"), got.astype(np.float32))
+    c.close()
+
+
 @pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("n,p,m,t", [(200, 2, 333, 37), (77, 3, 100, 5), (130, 5, 129, 17),
                                      (96, 8, 70, 33), (64, 13, 40, 9), (150, 20, 35, 18)])
