@@ -76,22 +76,21 @@ template <> struct DmaFrag<GWAS_FORM_F64> { using type = double2; using acc = d4
 template <> struct DmaFrag<GWAS_FORM_F32> { using type = float4; using acc = f4; };
 template <> struct DmaFrag<GWAS_FORM_BF16X3> { using type = bf16x8; using acc = f4; };
 
-// One workgroup per TM x TN tile. Workgroups are dispatched round-robin over
-// the chip's 8 XCDs (workgroup b on XCD b mod 8), each with its own L2; with
-// xcd_order, XCD x takes a contiguous eighth of the trait tiles and walks every
-// SNP tile, so its trait panels stay in its L2 while the SNP rows stream.
+// One TM x TN tile of problems (tile index over the tiles of a, traits fastest),
+// computed by a whole workgroup of C::NT threads with `lds` (C::LDS bytes,
+// 1 KB aligned) as its staging memory. Every thread of the workgroup calls it
+// with the same arguments (it contains workgroup barriers); on return all of
+// its global->LDS loads have completed and its LDS is no longer read.
 template <int FORM, int P, bool FLUSH, class T>
-__global__ __launch_bounds__((DmaCfg<FORM, P, T>::NT)) void fused_dma_kernel(FusedArgs a) {
+__device__ __forceinline__ void dma_tile(const FusedArgs &a, int64_t tile, uint8_t *lds) {
     using C = DmaCfg<FORM, P, T>;
     using frag = typename DmaFrag<FORM>::type;
     using acc_t = typename DmaFrag<FORM>::acc;
     constexpr int NQ = C::NQ, TM = C::TM, TN = C::TN, FM = C::FM, FN = C::FN, KB = C::KB, NA = C::NA;
     constexpr bool BF = C::BF;
     static_assert(!FLUSH || (FORM == GWAS_FORM_F32 && KB == 2), "the FP64 fold is per 32-sample FP32 window");
-    extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
 
     const int ntn = (a.tb + TN - 1) / TN;
-    const int64_t tile = xcd_order(blockIdx.x, ntn);
     const int tn = (int)(tile % ntn);
     const int64_t tm = tile / ntn;
     const int64_t m_base = tm * TM;
@@ -285,6 +284,17 @@ __global__ __launch_bounds__((DmaCfg<FORM, P, T>::NT)) void fused_dma_kernel(Fus
     else
         fused_epilogue<FORM, P, FM, FN>(a, [&](int q, int x, int y, int r) { return (double)acc[q][x][y][r]; },
                                         m_base, n_base, wm, wn, l16, g);
+}
+
+// One workgroup per tile. Workgroups are dispatched round-robin over the
+// chip's 8 XCDs (workgroup b on XCD b mod 8), each with its own L2; with
+// xcd_order, XCD x takes a contiguous eighth of the trait tiles and walks every
+// SNP tile, so its trait panels stay in its L2 while the SNP rows stream.
+template <int FORM, int P, bool FLUSH, class T>
+__global__ __launch_bounds__((DmaCfg<FORM, P, T>::NT)) void fused_dma_kernel(FusedArgs a) {
+    extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
+    const int ntn = (a.tb + DmaCfg<FORM, P, T>::TN - 1) / DmaCfg<FORM, P, T>::TN;
+    dma_tile<FORM, P, FLUSH, T>(a, xcd_order(blockIdx.x, ntn), lds);
 }
 
 template <int FORM, int P, bool FLUSH, class T>

@@ -8,22 +8,25 @@
 // any mix, so its results are the same).
 #include "serve.h"
 
-#include "fused.h"
+#include "fused_dma.h"
 
 namespace gw {
 namespace {
 
+// Tile code of the direct solve (fused_dma.h) with one workgroup shape for all
+// p of a launch: 4 waves of one 16x16 block each, 64 SNPs x 16 traits per tile
+// (requests have few traits, so narrow trait tiles waste little).
 template <int FORM, bool FLUSH>
-struct ServeTile;
-template <> struct ServeTile<GWAS_FORM_F64, false> { using type = Tile<4, 1, 1, 1, 128, 1>; };
-template <> struct ServeTile<GWAS_FORM_F32, true> { using type = Tile<4, 1, 1, 1, 128, 0>; };
-template <> struct ServeTile<GWAS_FORM_F32, false> { using type = Tile<2, 2, 2, 2, 128, 0>; };
-template <> struct ServeTile<GWAS_FORM_BF16X3, false> { using type = Tile<4, 1, 1, 1, 64, 0>; };
+struct ServeTile {
+    using type = typename std::conditional<FORM == GWAS_FORM_F64, DmaTile<4, 1, 1, 1, 1>,
+                 typename std::conditional<FORM == GWAS_FORM_F32, DmaTile<4, 1, 1, 1, 2, true>,
+                                           DmaTile<4, 1, 1, 1, 1, true>>::type>::type;
+};
 
 template <int FORM, bool FLUSH>
 struct ServeCfg {
     using T = typename ServeTile<FORM, FLUSH>::type;
-    using C8 = FusedCfg<FORM, kServeMaxP, T>;   // the largest p needs the most LDS
+    using C8 = DmaCfg<FORM, kServeMaxP, T>;   // the largest p needs the most LDS
     static constexpr int NT = C8::NT;
     static constexpr int LDS = C8::LDS;
 };
@@ -31,7 +34,7 @@ struct ServeCfg {
 template <int FORM, bool FLUSH>
 __global__ __launch_bounds__((ServeCfg<FORM, FLUSH>::NT)) void serve_kernel(ServeBatch bt) {
     using T = typename ServeTile<FORM, FLUSH>::type;
-    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
     __shared__ unsigned int next;
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(bt.counter, 1u);
@@ -61,13 +64,13 @@ __global__ __launch_bounds__((ServeCfg<FORM, FLUSH>::NT)) void serve_kernel(Serv
         fa.f32_flush = bt.f32_flush;
         const int64_t local = tile - s.tile0;
         switch (s.p) {
-        case 2: fused_tile<FORM, 2, FLUSH, T>(fa, local, lds); break;
-        case 3: fused_tile<FORM, 3, FLUSH, T>(fa, local, lds); break;
-        case 4: fused_tile<FORM, 4, FLUSH, T>(fa, local, lds); break;
-        case 5: fused_tile<FORM, 5, FLUSH, T>(fa, local, lds); break;
-        case 6: fused_tile<FORM, 6, FLUSH, T>(fa, local, lds); break;
-        case 7: fused_tile<FORM, 7, FLUSH, T>(fa, local, lds); break;
-        default: fused_tile<FORM, 8, FLUSH, T>(fa, local, lds); break;
+        case 2: dma_tile<FORM, 2, FLUSH, T>(fa, local, lds); break;
+        case 3: dma_tile<FORM, 3, FLUSH, T>(fa, local, lds); break;
+        case 4: dma_tile<FORM, 4, FLUSH, T>(fa, local, lds); break;
+        case 5: dma_tile<FORM, 5, FLUSH, T>(fa, local, lds); break;
+        case 6: dma_tile<FORM, 6, FLUSH, T>(fa, local, lds); break;
+        case 7: dma_tile<FORM, 7, FLUSH, T>(fa, local, lds); break;
+        default: dma_tile<FORM, 8, FLUSH, T>(fa, local, lds); break;
         }
     }
 }
@@ -90,10 +93,10 @@ template <int FORM, bool FLUSH>
 void tile_shape_t(int p, int &tm, int &tn) {
     using T = typename ServeTile<FORM, FLUSH>::type;
     switch (p) {
-#define GW_SHAPE(PP) case PP: tm = FusedCfg<FORM, PP, T>::TM; tn = FusedCfg<FORM, PP, T>::TN; return;
+#define GW_SHAPE(PP) case PP: tm = DmaCfg<FORM, PP, T>::TM; tn = DmaCfg<FORM, PP, T>::TN; return;
         GW_SHAPE(2) GW_SHAPE(3) GW_SHAPE(4) GW_SHAPE(5) GW_SHAPE(6) GW_SHAPE(7)
 #undef GW_SHAPE
-    default: tm = FusedCfg<FORM, 8, T>::TM; tn = FusedCfg<FORM, 8, T>::TN; return;
+    default: tm = DmaCfg<FORM, 8, T>::TM; tn = DmaCfg<FORM, 8, T>::TN; return;
     }
 }
 
