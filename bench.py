@@ -221,7 +221,7 @@ def main():
     ap.add_argument("--slots", type=int, default=8, help="serving: requests in flight")
     ap.add_argument("--ring-slots", type=int, default=0, help="serving: pinned ring slots (0: library default)")
     ap.add_argument("--skip-checksum", action="store_true", help="serving: do not checksum ring slabs")
-    ap.add_argument("--grid-wgs", type=int, default=0, help="serving: persistent workgroups (0: one per CU)")
+    ap.add_argument("--grid-wgs", type=int, default=0, help="serving: persistent workgroups (0: two per CU)")
     ap.add_argument("--profile-pass", action="store_true",
                     help="one step of the headline form plus a plain 1 GiB device copy (for counter "
                          "calibration), no timing output; meant to run under rocprofv3")

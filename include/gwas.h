@@ -259,8 +259,8 @@ typedef struct gwas_server_options {
     int32_t ring_slots;  /* pinned host ring slots; 0: 2 x max_slots                       */
     int32_t host_threads;/* checksum worker threads (one ring slab each at a time); 0: 8    */
     int32_t skip_checksum; /* nonzero: ring slabs are handed to the callback unchecksummed */
-    int32_t grid_wgs;    /* persistent workgroups per launch; 0: one per compute unit, which
-                            leaves room on every unit for the device->host copy kernels  */
+    int32_t grid_wgs;    /* persistent workgroups per launch; 0: two per compute unit
+                            (measured best; the copy kernels still get their share)      */
     int32_t reserved[4];
 } gwas_server_options;
 

@@ -30,7 +30,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 template <bool F64>
 __device__ __forceinline__ int mfma16_row(int g, int r) { return F64 ? g + 4 * r : 4 * g + r; }
 
-// Workgroup -> tile order over ntn column tiles (see fused.h): XCD-aware when
+// Workgroup -> tile order over ntn column tiles (see fused_dma.h): XCD-aware when
 // ntn is a multiple of 8, identity otherwise; a bijection of [0, tiles).
 __device__ __forceinline__ int64_t xcd_order(int64_t b, int ntn) {
     if (ntn % 8) return b;

@@ -567,7 +567,7 @@ gwas_status gwas_server_create(gwas_ctx *c, const gwas_server_options *opt, gwas
     hipError_t e = hipSetDevice(c->dev);
     int cus = 256;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->dev);
-    s->grid = opt->grid_wgs > 0 ? opt->grid_wgs : cus;
+    s->grid = opt->grid_wgs > 0 ? opt->grid_wgs : 2 * cus;
     if (e == hipSuccess) e = hipMalloc(&s->arena_mem, budget);
     if (e == hipSuccess) e = hipMalloc((void **)&s->d_counter, 256);
     // The copy stream must not share a hardware queue with the compute stream, or
