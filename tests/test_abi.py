@@ -43,3 +43,19 @@ def test_binding_refuses_to_run_without_the_library(monkeypatch, tmp_path):
     monkeypatch.setattr(gwas, "_lib", None)
     with pytest.raises(ImportError):
         gwas.load()
+
+
+@pytest.mark.parametrize("bad", [1, 3, 4])
+def test_setup_rejects_fold_intervals_other_than_0_and_2(bad):
+    """Option checks run before any device call, so this needs no GPU."""
+    import numpy as np
+
+    from paper_1210_7683_amd import gwas
+    if not os.path.exists(gwas.LIB_PATH):
+        pytest.fail("libgwas.so is not built; run python -m paper_1210_7683_amd.build")
+    n = 8
+    z = np.eye(n)
+    w = np.ones(n)
+    xl = np.ones((1, n))
+    with pytest.raises(gwas.GwasError, match="f32_flush"):
+        gwas.Cohort(z, w, xl, 4, forms=("f32",), f32_flush=bad)
