@@ -90,7 +90,10 @@ typedef struct gwas_stats_t {
     double fused_ms;        /* their summed duration, ms                                 */
     int64_t rotate_launches;/* timed launches of the rotation kernel                     */
     double rotate_ms;       /* their summed duration, ms                                 */
-    int64_t reserved[6];
+    int64_t dot_launches;   /* launches of the dot-product kernel: FP64 and FP32 solve
+                               calls with at most 3 traits (whose (p+1) x t x n_pad
+                               panels fit 64 KB) use it instead of the MFMA tiles      */
+    int64_t reserved[5];
 } gwas_stats_t;
 
 /* Fill *opt with defaults (m_capacity must still be set). */

@@ -319,7 +319,7 @@ gwas_status prep_traits(gwas_ctx *c, int j0, int jb, const double *Y, int32_t y_
     return GWAS_OK;
 }
 
-FusedArgs fused_args(gwas_ctx *c, int jb, int32_t form) {
+FusedArgs fused_args(gwas_ctx *c, int jb, int32_t form, int tb_call) {
     FusedArgs fa{};
     fa.a = form == GWAS_FORM_F64 ? (const void *)c->xr64
          : form == GWAS_FORM_F32 ? (const void *)c->xr32 : (const void *)c->xrbf;
@@ -334,6 +334,7 @@ FusedArgs fused_args(gwas_ctx *c, int jb, int32_t form) {
     fa.rank_rtol = kRankRtol[form];
     fa.non_spd = c->counters;
     fa.f32_flush = form == GWAS_FORM_F32 ? c->f32_flush : 0;
+    fa.small_t = use_dot_kernel(form, c->p, tb_call, c->n_pad);
     return fa;
 }
 
@@ -341,6 +342,7 @@ gwas_status launch_fused_timed(gwas_ctx *c, int32_t form, const FusedArgs &fa, h
     std::pair<hipEvent_t, hipEvent_t> ev{};
     HIP_TRY(timed_begin(c, s, ev));
     HIP_TRY(launch_fused(form, fa, s));
+    if (fa.small_t) ++c->dot_launches;
     HIP_TRY(timed_end(c, s, ev, c->t_fused));
     return GWAS_OK;
 }
@@ -381,7 +383,7 @@ gwas_status gwas_solve(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, const do
     for (int j0 = 0; j0 < tb; j0 += c->tcap) {
         const int jb = std::min(c->tcap, tb - j0);
         if ((st = prep_traits(c, j0, jb, Y, y_on_device, h2, form, s)) != GWAS_OK) return st;
-        FusedArgs fa = fused_args(c, jb, form);
+        FusedArgs fa = fused_args(c, jb, form, tb);
         if (b_on_device) {
             fa.i0 = i0;
             fa.mi = mi;
@@ -469,7 +471,7 @@ gwas_status gwas_solve_stream(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, c
     for (int j0 = 0; j0 < tb; j0 += c->tcap) {
         const int jb = std::min(c->tcap, tb - j0);
         if ((st = prep_traits(c, j0, jb, Y, y_on_device, h2, form, s)) != GWAS_OK) return st;
-        FusedArgs fa = fused_args(c, jb, form);
+        FusedArgs fa = fused_args(c, jb, form, tb);
         for (int64_t s0 = 0; s0 < mi; s0 += c->slab, dslot ^= 1) {
             const int64_t cnt = std::min<int64_t>(c->slab, mi - s0);
             const int rslot = (int)(issued % R);
@@ -545,6 +547,7 @@ gwas_status gwas_stats(gwas_ctx *c, gwas_stats_t *out) {
     out->non_spd = (int64_t)cnt[0];
     out->snps_rotated = c->snps_rotated;
     out->problems = c->problems;
+    out->dot_launches = c->dot_launches;
     out->bytes_h2d = c->bytes_h2d;
     out->bytes_d2h = c->bytes_d2h;
     out->resident_bytes = c->resident;
@@ -574,7 +577,7 @@ gwas_status gwas_reset_stats(gwas_ctx *c) {
     int64_t cnt;
     drain(c, c->t_fused, cnt);
     drain(c, c->t_rot, cnt);
-    c->snps_rotated = c->problems = c->bytes_h2d = c->bytes_d2h = 0;
+    c->snps_rotated = c->problems = c->bytes_h2d = c->bytes_d2h = c->dot_launches = 0;
     return GWAS_OK;
 }
 

@@ -116,7 +116,7 @@ struct gwas_ctx {
     size_t ring_bytes = 0;
     std::vector<hipEvent_t> ring_ev;
 
-    int64_t snps_rotated = 0, problems = 0, bytes_h2d = 0, bytes_d2h = 0, resident = 0;
+    int64_t snps_rotated = 0, problems = 0, bytes_h2d = 0, bytes_d2h = 0, resident = 0, dot_launches = 0;
 
     // optional per-launch timing: event pairs recorded around launches
     bool timing = false;

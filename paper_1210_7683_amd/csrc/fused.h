@@ -43,6 +43,55 @@ __device__ __forceinline__ void square_split(const bf16x8 &h, const bf16x8 &l, b
     }
 }
 
+// The p x p solve of one problem (i, j) from its p+1 contractions cq (FP64):
+//   u = L_j^{-1} S_BL;  s = S_BR - u.u;  beta = (b_B - u.z_j) / s;
+//   b_top = L_j^{-T} (z_j - u beta)
+// with Lf(k) the packed lower triangle of L_j^{-1} and z = z_j. Stores b_ij
+// (NaN when the pivot s falls below rank_rtol * S_BR or is not finite) and
+// returns whether it was finite.
+template <int FORM, int P, class LF>
+__device__ __forceinline__ bool gls_solve_store(const FusedArgs &a, const double *cq, LF Lf, const double *z,
+                                                int64_t i, int j) {
+    constexpr int Q = P - 1;
+    double u[Q];
+    double s = cq[0];
+#pragma unroll
+    for (int aa = 0; aa < Q; ++aa) {
+        double v = 0.0;
+#pragma unroll
+        for (int bb = 0; bb <= aa; ++bb) v += Lf(aa * (aa + 1) / 2 + bb) * cq[1 + bb];
+        u[aa] = v;
+        s -= v * v;
+    }
+    double num = cq[P];
+#pragma unroll
+    for (int aa = 0; aa < Q; ++aa) num -= u[aa] * z[aa];
+    const bool ok = (s > a.rank_rtol * cq[0]) && isfinite(s) && isfinite(num);
+    const double beta = num / s;
+    double out[P];
+#pragma unroll
+    for (int aa = 0; aa < Q; ++aa) u[aa] = z[aa] - u[aa] * beta;
+#pragma unroll
+    for (int bb = 0; bb < Q; ++bb) {
+        double v = 0.0;
+#pragma unroll
+        for (int aa = bb; aa < Q; ++aa) v += Lf(aa * (aa + 1) / 2 + bb) * u[aa];
+        out[bb] = v;
+    }
+    out[Q] = beta;
+    const int64_t o = (i * a.ldt + j) * P;
+    if constexpr (FORM == GWAS_FORM_F64) {
+        double *bo = (double *)a.b + o;
+#pragma unroll
+        for (int v = 0; v < P; ++v) bo[v] = ok ? out[v] : __builtin_nan("");
+    } else {
+        float *bo = (float *)a.b + o;
+#pragma unroll
+        for (int v = 0; v < P; ++v) bo[v] = ok ? (float)out[v] : __builtin_nanf("");
+    }
+    return ok;
+}
+
 // FP64 epilogue: Gram assembly and the p x p solve, lane-local. get(q, x, y,
 // r) returns contraction q of register slot r of the wave's MFMA block (x, y).
 template <int FORM, int P, int FM, int FN, class Get>
@@ -79,43 +128,7 @@ __device__ __forceinline__ void fused_epilogue(const FusedArgs &a, Get get, int6
                 double cq[P + 1];
 #pragma unroll
                 for (int q = 0; q <= P; ++q) cq[q] = get(q, x, y, r);
-                double u[Q];
-                double s = cq[0];
-#pragma unroll
-                for (int aa = 0; aa < Q; ++aa) {
-                    double v = 0.0;
-#pragma unroll
-                    for (int bb = 0; bb <= aa; ++bb) v += Lf(aa * (aa + 1) / 2 + bb) * cq[1 + bb];
-                    u[aa] = v;
-                    s -= v * v;
-                }
-                double num = cq[P];
-#pragma unroll
-                for (int aa = 0; aa < Q; ++aa) num -= u[aa] * z[aa];
-                const bool ok = (s > a.rank_rtol * cq[0]) && isfinite(s) && isfinite(num);
-                const double beta = num / s;
-                double out[P];
-#pragma unroll
-                for (int aa = 0; aa < Q; ++aa) u[aa] = z[aa] - u[aa] * beta;
-#pragma unroll
-                for (int bb = 0; bb < Q; ++bb) {
-                    double v = 0.0;
-#pragma unroll
-                    for (int aa = bb; aa < Q; ++aa) v += Lf(aa * (aa + 1) / 2 + bb) * u[aa];
-                    out[bb] = v;
-                }
-                out[Q] = beta;
-                const int64_t o = (i * a.ldt + j) * P;
-                if constexpr (FORM == GWAS_FORM_F64) {
-                    double *bo = (double *)a.b + o;
-#pragma unroll
-                    for (int v = 0; v < P; ++v) bo[v] = ok ? out[v] : __builtin_nan("");
-                } else {
-                    float *bo = (float *)a.b + o;
-#pragma unroll
-                    for (int v = 0; v < P; ++v) bo[v] = ok ? (float)out[v] : __builtin_nanf("");
-                }
-                bad += ok ? 0u : 1u;
+                bad += gls_solve_store<FORM, P>(a, cq, Lf, z, i, j) ? 0u : 1u;
             }
         }
     if (bad) atomicAdd(a.non_spd, (unsigned long long)bad);

@@ -1,4 +1,4 @@
-// Instantiations of the fused contraction + solve kernel for one form, p = 2..20.
+// Instantiations of the fused contraction + solve kernels for one form, p = 2..20.
 #include "fused_dma.h"
 
 namespace gw {

@@ -290,24 +290,21 @@ __device__ __forceinline__ void dma_tile(const FusedArgs &a, int64_t tile, uint8
 // chip's 8 XCDs (workgroup b on XCD b mod 8), each with its own L2; with
 // xcd_order, XCD x takes a contiguous eighth of the trait tiles and walks every
 // SNP tile, so its trait panels stay in its L2 while the SNP rows stream.
-// The grid is padded to a multiple of 8 trait tiles per SNP tile so that this
-// holds for any trait count; the padding workgroups exit at once.
+// tile_order applies it to the largest multiple of 8 trait tiles and runs the
+// rest (fewer than 8 per SNP tile) after them.
 template <int FORM, int P, bool FLUSH, class T>
 __global__ __launch_bounds__((DmaCfg<FORM, P, T>::NT)) void fused_dma_kernel(FusedArgs a) {
+    using C = DmaCfg<FORM, P, T>;
     extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
-    const int ntn = (a.tb + DmaCfg<FORM, P, T>::TN - 1) / DmaCfg<FORM, P, T>::TN;
-    const int ntn8 = (ntn + 7) / 8 * 8;
-    const int64_t t8 = xcd_order(blockIdx.x, ntn8);
-    const int tn = (int)(t8 % ntn8);
-    if (tn >= ntn) return;   // padding (uniform over the workgroup)
-    dma_tile<FORM, P, FLUSH, T>(a, (t8 / ntn8) * ntn + tn, lds);
+    const int ntn = (a.tb + C::TN - 1) / C::TN;
+    const int64_t ntm = (a.mi + C::TM - 1) / C::TM;
+    dma_tile<FORM, P, FLUSH, T>(a, tile_order(blockIdx.x, ntm, ntn), lds);
 }
 
 template <int FORM, int P, bool FLUSH, class T>
 hipError_t launch_dma_t(const FusedArgs &a, hipStream_t s) {
     using C = DmaCfg<FORM, P, T>;
-    const int64_t ntn8 = ((a.tb + C::TN - 1) / C::TN + 7) / 8 * 8;
-    const int64_t tiles = ((a.mi + C::TM - 1) / C::TM) * ntn8;
+    const int64_t tiles = ((a.mi + C::TM - 1) / C::TM) * ((a.tb + C::TN - 1) / C::TN);
     if (a.mi <= 0 || a.tb <= 0) return hipSuccess;
     if ((a.n_pad * C::ESZ) % (C::KB * 64)) return hipErrorInvalidValue;
     if (C::LDS > 65536) {

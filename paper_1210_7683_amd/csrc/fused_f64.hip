@@ -1,9 +1,11 @@
-// Instantiations of the fused contraction + solve kernel for one form, p = 2..20.
+// Instantiations of the fused contraction + solve kernels for one form, p = 2..20.
 #include "fused_dma.h"
+#include "fused_gemv.h"
 
 namespace gw {
 
 hipError_t launch_fused_f64(const FusedArgs &a, hipStream_t s) {
+    if (a.small_t) return dispatch_gemv<GWAS_FORM_F64>(a, s);
     return dispatch_dma<GWAS_FORM_F64, false>(a, s);
 }
 

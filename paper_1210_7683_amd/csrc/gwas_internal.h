@@ -39,6 +39,24 @@ __device__ __forceinline__ int64_t xcd_order(int64_t b, int ntn) {
     return (local / g) * ntn + x * g + local % g;
 }
 
+// Workgroup -> tile (tm * ntn + tn) over ntm x ntn tiles, a bijection for any
+// ntn: the first 8 floor(ntn / 8) column tiles of every row in XCD-aware order
+// (each XCD a contiguous eighth of them), the remaining ntn mod 8 after them in
+// plain order; fewer than 8 column tiles: plain order.
+__device__ __forceinline__ int64_t tile_order(int64_t b, int64_t ntm, int ntn) {
+    const int g = ntn / 8;
+    if (g == 0) return b;
+    const int n8 = 8 * g;
+    const int64_t na = ntm * n8;
+    if (b < na) {
+        const int64_t t = xcd_order(b, n8);
+        return (t / n8) * ntn + t % n8;
+    }
+    const int r = ntn - n8;
+    b -= na;
+    return (b / r) * ntn + n8 + b % r;
+}
+
 // Round-to-nearest-even of an FP32 value to BF16 (finite inputs), as raw bits.
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
     uint32_t u = __float_as_uint(x);
@@ -101,8 +119,22 @@ struct FusedArgs {
     double rank_rtol;
     unsigned long long *non_spd;
     int f32_flush;
+    int small_t;            // nonzero: the call has at most kSmallT traits (dot-product kernel)
 };
 hipError_t launch_fused(int form, const FusedArgs &a, hipStream_t s);
+
+// FP64 and FP32 solve calls with at most kSmallT traits in total, whose panels
+// fit the dot-product kernel's LDS copy, use that kernel (HBM-bound,
+// fused_gemv.h) instead of the MFMA tiles; measured on MI355X at n = 1000,
+// p = 4, it is faster there (the split-BF16 MFMA tiles are not slower at any
+// t). The choice is per call, so every problem of a call is computed the same
+// way whatever the sub-blocking.
+constexpr int kSmallT = 3;
+constexpr int64_t kGemvLdsMax = 64 * 1024;
+inline bool use_dot_kernel(int form, int p, int tb_call, int n_pad) {
+    const int64_t lds = (int64_t)(p + 1) * tb_call * n_pad * (form == GWAS_FORM_F64 ? 8 : 4);
+    return form != GWAS_FORM_BF16X3 && tb_call <= kSmallT && lds <= kGemvLdsMax;
+}
 
 // Copy `bytes` (a multiple of 4; 16-byte aligned pointers) from device memory
 // to pinned host memory, given the host buffer's device-side address.

@@ -186,7 +186,7 @@ __global__ __launch_bounds__(R::NT) void rotate_u8_dma_kernel(const uint8_t *__r
     constexpr int TN = R::TN, FM = R::FM, FN = R::FN;
     extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
     const int ntn = n_pad / TN;
-    const int64_t tile = xcd_order(blockIdx.x, ntn);
+    const int64_t tile = tile_order(blockIdx.x, (rows + R::TM - 1) / R::TM, ntn);
     const int tn = (int)(tile % ntn);
     const int64_t tm = tile / ntn;
     const int64_t i_base = tm * R::TM;

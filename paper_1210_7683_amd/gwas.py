@@ -83,7 +83,7 @@ class Stats(ctypes.Structure):
                 ("bytes_d2h", ctypes.c_int64), ("resident_bytes", ctypes.c_int64),
                 ("fused_launches", ctypes.c_int64), ("fused_ms", ctypes.c_double),
                 ("rotate_launches", ctypes.c_int64), ("rotate_ms", ctypes.c_double),
-                ("reserved", ctypes.c_int64 * 6)]
+                ("dot_launches", ctypes.c_int64), ("reserved", ctypes.c_int64 * 5)]
 
 
 def load():

@@ -117,6 +117,49 @@ def test_ragged_shapes_and_p(form, n, p, m, t, torch_cuda):
 
 
 @pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("n,p,m,t", [(200, 2, 333, 1), (77, 4, 100, 2), (130, 9, 129, 3),
+                                     (1000, 4, 70, 1), (1000, 4, 70, 4), (64, 20, 40, 1),
+                                     (96, 13, 65, 3)])
+def test_small_trait_calls_use_the_dot_product_kernel(form, n, p, m, t, torch_cuda):
+    """FP64 and FP32 solve calls with t <= 3 traits whose panels fit 64 KB run
+    the dot-product kernel (counted in the stats); every case: parity with the
+    oracle at the form's tolerance, ragged m and n, and the device, sub-range and
+    host-slab outputs agree bitwise."""
+    torch = torch_cuda
+    phi, xl, xr, y, h2 = synth.small(n, p, m, t, seed=n * 7 + p + t)
+    ref = oracle.gls_grid(phi, xl, xr, y, h2)
+    c = cohort(phi, xl, xr, forms=(form,), slab_snps=32)
+    b = c.solve(y, h2, form=form).cpu().numpy()
+    n_pad = (n + 63) // 64 * 64
+    dot = form != "bf16x3" and t <= 3 and (p + 1) * t * n_pad * (8 if form == "f64" else 4) <= 64 * 1024
+    assert c.stats()["dot_launches"] == (1 if dot else 0)
+    err, sc = rel_err(b, ref), scaled_err(b, ref)
+    print("n=%d p=%d m=%d t=%d %s: relative max %.3e, scaled max %.3e" % (n, p, m, t, form,
+                                                                       err.max(), sc.max()))
+    assert sc.max() <= TOL[form]
+    assert np.quantile(err, 0.99) <= TOL[form]
+    part = c.solve(y, h2, form=form, i0=3, m=m - 5).cpu().numpy()
+    assert np.array_equal(part, b[3:m - 2])
+    dt = torch.float64 if form == "f64" else torch.float32
+    host = torch.empty((m, t, p), dtype=dt, pin_memory=True)
+    c.solve(y, h2, form=form, out=host)
+    torch.cuda.synchronize()
+    assert np.array_equal(host.numpy(), b)
+    c.close()
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_calls_with_four_traits_use_the_mfma_tiles(form, torch_cuda):
+    phi, xl, xr, y, h2 = synth.small(128, 4, 100, 4, seed=11)
+    ref = oracle.gls_grid(phi, xl, xr, y, h2)
+    c = cohort(phi, xl, xr, forms=(form,), max_traits=3)   # sub-blocks of 3 and 1 traits
+    b = c.solve(y, h2, form=form).cpu().numpy()
+    assert c.stats()["dot_launches"] == 0
+    assert scaled_err(b, ref).max() <= TOL[form]
+    c.close()
+
+
+@pytest.mark.parametrize("form", FORMS)
 def test_subranges_and_trait_subblocks_are_bitwise_consistent(form, torch_cuda):
     torch = torch_cuda
     phi, xl, xr, y, h2 = synth.small(160, 4, 300, 70, seed=5)
