@@ -143,6 +143,71 @@ def stream_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def single_trait_bench(args):
+    """One trait (t = 1) against m = 1e6 resident SNPs, n = 1000, p = 4: the
+    dot-product kernel, bound by reading the rotated SNP store once. A step is
+    one solve of the m x 1 grid (the rotation is the cohort's one-time setup,
+    timed separately); the roofline is HBM bytes per launch over its duration."""
+    import torch
+
+    import synth
+    from paper_1210_7683_amd import gwas
+
+    w = synth.WORKLOADS[args.workload]
+    forms = [f for f in args.forms.split(",") if f in ("f32", "f64")] or ["f32"]
+    t0 = time.perf_counter()
+    phi, xl = synth.kinship(w), synth.covariates(w)
+    xr = synth.snps(w)
+    y, h2 = synth.traits(w)
+    ev, z = np.linalg.eigh(phi)
+    log("inputs (%d SNPs, %d trait) drawn in %.1f s" % (w.m, w.t, time.perf_counter() - t0))
+    xr_d = torch.from_numpy(xr).cuda()
+    y_d = torch.from_numpy(y).cuda()
+    results = {}
+    for form in forms:
+        cohort = gwas.Cohort(z, ev, xl, w.m, forms=(form,), timing=True)
+        cohort.rotate(0, xr_d)
+        dt = torch.float64 if form == "f64" else torch.float32
+        b = torch.empty((w.m, w.t, w.p), dtype=dt, device="cuda")
+        torch.cuda.synchronize()
+        rot_ms = cohort.stats()["rotate_ms"]
+        for _ in range(args.warmup):
+            cohort.solve(y_d, h2, form=form, out=b)
+        torch.cuda.synchronize()
+        cohort.reset_stats()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            cohort.solve(y_d, h2, form=form, out=b)
+        e1.record()
+        torch.cuda.synchronize()
+        st = cohort.stats()
+        ms = e0.elapsed_time(e1) / args.steps
+        fused_ms = st["fused_ms"] / max(1, st["fused_launches"])
+        esz = 8 if form == "f64" else 4
+        bytes_launch = w.m * (w.n * esz + w.t * w.p * esz)   # X'_R rows once + b
+        results[form] = {"gls_per_s": w.m * w.t / (ms * 1e-3), "ms_per_step": ms, "fused_ms": fused_ms,
+                         "hbm_gbps": bytes_launch / (fused_ms * 1e-3) / 1e9, "dot_launches": st["dot_launches"],
+                         "rotate_once_ms": rot_ms, "finite": bool(torch.isfinite(b).all().item())}
+        log("%s: %.3f ms/solve (kernel %.3f ms, %.0f GB/s), %.3g GLS/s; rotation once %.1f ms" %
+            (form, ms, fused_ms, results[form]["hbm_gbps"], results[form]["gls_per_s"], rot_ms))
+        cohort.close()
+        del b
+    head = forms[0]
+    r = results[head]
+    line = {"metric": "GLS problems/s, single trait (t = 1) against a resident cohort",
+            "value": r["gls_per_s"], "unit": "GLS problems/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": head, "data": "synthetic",
+            "config": {"workload": w.name, "n": w.n, "p": w.p, "m": w.m, "t": w.t, "form": head,
+                       "step": "solve of the m x 1 grid, rotated SNPs resident, b in HBM"},
+            "roofline": {"bound": "hbm", "achieved": r["hbm_gbps"], "peak": HBM_GBPS, "unit": "GB/s",
+                         "frac": r["hbm_gbps"] / HBM_GBPS, "traffic": None,
+                         "kernel": "fused_gemv_kernel<%s, p=4, t=1>" % head},
+            "forms": results}
+    print(json.dumps(line), flush=True)
+
+
 def serve_bench(args):
     """Serving: resident cohort n = 1000, m = 1e6; Poisson arrivals; each request a
     trait block with t ~ log-uniform[1, 512], its own h2 and p - 1 ~ U{1..7}; b
@@ -242,6 +307,10 @@ def main():
         if args.forms == "f32,f64,bf16x3":
             args.forms = "bf16x3"
         return stream_bench(args)
+    if args.workload.startswith("single_trait"):
+        if args.forms == "f32,f64,bf16x3":
+            args.forms = "f32,f64"
+        return single_trait_bench(args)
     if args.workload.startswith("serve"):
         if args.forms == "f32,f64,bf16x3":
             args.forms = "f32"

@@ -57,3 +57,22 @@ def test_precision_study_paper_m1e6():
             print("PRECISION " + json.dumps(stats), flush=True)
             assert finite
             assert e.max() <= TOL[form], stats
+        # single-trait calls (the dot-product kernel in the FP64 and FP32 forms)
+        rng = np.random.default_rng(5)
+        i1 = np.sort(rng.choice(w.m, size=10_000, replace=False))
+        ref1 = oracle.gls(phi, xl, xr[i1], y[:1], h2[:1], trait=np.zeros(i1.size, dtype=np.int64))
+        t1 = torch.from_numpy(i1).cuda()
+        for form in ("f64", "f32"):
+            c.reset_stats()
+            b = c.solve(yd[:1], h2[:1], form=form)
+            assert c.stats()["dot_launches"] == 1
+            got = b[t1, 0].cpu().numpy()
+            finite = bool(torch.isfinite(b).all())
+            del b
+            e = rel_err(got, ref1)
+            stats = {"form": form, "t": 1, "problems": int(e.size), "rel_max": float(e.max()),
+                     "rel_p9999": float(np.quantile(e, 0.9999)), "rel_median": float(np.median(e)),
+                     "all_finite": finite}
+            print("PRECISION " + json.dumps(stats), flush=True)
+            assert finite
+            assert e.max() <= TOL[form], stats
