@@ -74,9 +74,23 @@ def cpu_baseline(w, phi, xl, budget_s: float = 12.0):
         if dt >= budget_s / 3 or jj.size >= w.t:
             break
         count = int(min(w.t, max(count * 2, count * budget_s / max(dt, 1e-3))))
+    # one thread, a few problems of the same sample
+    k1 = min(8, jj.size)
+    t1 = time.perf_counter()
+    oracle.gls(phi, xl, xr[:k1], y[jj[:k1]], h2[jj[:k1]], nthreads=1)
+    dt1 = time.perf_counter() - t1
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": jj.size / dt, "unit": "GLS problems/s", "cores": threads, "kind": "oracle",
             "sample": "%d problems (i, j) of the %s workload with distinct traits, each factorising "
-                      "its own n x n M_j; %.1f s on %d threads" % (jj.size, w.name, dt, threads)}
+                      "its own n x n M_j; %.1f s on %d threads" % (jj.size, w.name, dt, threads),
+            "single_thread_value": k1 / dt1, "cpu_model": model}
 
 
 def stream_bench(args):
@@ -360,16 +374,17 @@ def main():
             step()
         torch.cuda.synchronize()
         cohort.reset_stats()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         torch.cuda.synchronize()
         w0 = time.perf_counter()
-        e0.record()
-        for _ in range(args.steps):
+        evs[0].record()
+        for k in range(args.steps):
             step()
-        e1.record()
+            evs[k + 1].record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
-        ms = e0.elapsed_time(e1) / args.steps
+        step_ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)])
+        ms = evs[0].elapsed_time(evs[-1]) / args.steps
         st = cohort.stats()
         fused_ms = st["fused_ms"] / max(1, st["fused_launches"])
         rot_ms = st["rotate_ms"] / max(1, st["rotate_launches"])
@@ -378,6 +393,9 @@ def main():
         results[form] = {
             "gls_per_s": problems / (ms * 1e-3),
             "ms_per_step": ms,
+            "step_ms_median": float(np.median(step_ms)),
+            "step_ms_min": float(step_ms.min()),
+            "step_ms_max": float(step_ms.max()),
             "wall_ms_per_step": wall * 1e3 / args.steps,
             "fused_ms": fused_ms,
             "rotate_ms": rot_ms,
