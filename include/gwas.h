@@ -188,6 +188,28 @@ gwas_status gwas_solve_stream(gwas_ctx *ctx, int64_t i0, int64_t mi, int32_t tb,
                               void *user, uint64_t *checksums, int64_t max_checksums, int64_t *n_slabs,
                               void *stream);
 
+/*
+ * Genotype stream: solve the grid of m SNPs that are not resident, held in host
+ * (or device) memory as X_R, n x m SNP-major of element type dtype, against the
+ * tb traits of Y. The SNPs pass through the context's rotated store in blocks
+ * of m_capacity / 2: block k is copied to the device and rotated by Z^T
+ * (Algorithm 5, preloop) into store half k % 2 on the library's own stream
+ * while block k - 1 is solved from the other half on `stream`, and b leaves
+ * slab by slab through the pinned ring exactly as in gwas_solve_stream (slab
+ * i0 is the SNP's index in X_R). This is the paper's streaming of the SNP
+ * matrix through memory (Section 4), with HBM as the buffer and the host as
+ * the backing store; m is unbounded by m_capacity. Overwrites the resident
+ * store. X_R is read by hipMemcpyAsync (any memory kind); pinned host memory
+ * lets the copies overlap the kernels. Same outputs as rotating all m SNPs and calling
+ * gwas_solve_stream (bitwise). Errors: those of gwas_solve_stream, and
+ * GWAS_EINVAL for m < 0, an unknown dtype or m_capacity < 2; GWAS_ENOMEM for
+ * the two block staging buffers (2 x m_capacity / 2 x n x element size).
+ */
+gwas_status gwas_solve_snp_stream(gwas_ctx *ctx, const void *X_R, int32_t dtype, int64_t m, int32_t tb,
+                                  const double *Y, int32_t y_on_device, const double *h2, int32_t form,
+                                  gwas_slab_fn fn, void *user, uint64_t *checksums, int64_t max_checksums,
+                                  int64_t *n_slabs, void *stream);
+
 /* The checksum used by gwas_solve_stream, over bytes (a multiple of 4) at p. */
 uint64_t gwas_checksum(const void *p, int64_t bytes);
 

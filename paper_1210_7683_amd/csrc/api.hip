@@ -80,13 +80,16 @@ void release(gwas_ctx *c) {
         }
     void *ptrs[] = {c->Z, c->w, c->xlt, c->xr64, c->xr32, c->xrbf, c->y_in, c->yt, c->h2,
                     c->panels[0], c->panels[1], c->panels[2], c->fac, c->counters, c->stage,
-                    c->bstage[0], c->bstage[1]};
+                    c->bstage[0], c->bstage[1], c->xin[0], c->xin[1]};
     for (void *p : ptrs)
         if (p) hipFree(p);
     for (int i = 0; i < 2; ++i) {
         if (c->ev_done[i]) hipEventDestroy(c->ev_done[i]);
         if (c->ev_free[i]) hipEventDestroy(c->ev_free[i]);
+        if (c->ev_rot[i]) hipEventDestroy(c->ev_rot[i]);
+        if (c->ev_half[i]) hipEventDestroy(c->ev_half[i]);
     }
+    if (c->aux) hipStreamDestroy(c->aux);
     if (c->ev_side) hipEventDestroy(c->ev_side);
     for (void *p : c->ring)
         if (p) hipHostFree(p);
@@ -419,22 +422,30 @@ gwas_status gwas_solve(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, const do
     return GWAS_OK;
 }
 
-gwas_status gwas_solve_stream(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, const double *Y,
-                              int32_t y_on_device, const double *h2, int32_t form, gwas_slab_fn fn,
-                              void *user, uint64_t *checksums, int64_t max_checksums, int64_t *n_slabs,
-                              void *stream) {
-    last_error().clear();
-    gwas_status st = check_solve(c, i0, mi, tb, Y, y_on_device, h2, form);
-    if (st != GWAS_OK) return st;
-    if (n_slabs) *n_slabs = 0;
-    if (mi == 0) return GWAS_OK;
-    HIP_TRY(hipSetDevice(c->dev));
-    hipStream_t s = (hipStream_t)stream;
-    const int p = c->p;
-    const size_t besz = form == GWAS_FORM_F64 ? 8 : 4;
-    if ((st = ensure_bstage(c)) != GWAS_OK) return st;
-    const int R = c->ring_slots;
-    if (c->ring.empty()) {
+namespace {
+
+// The streamed sink: a pinned host ring (library-owned, allocated on first
+// use) and the slabs in flight, consumed in issue order on the calling thread.
+struct RingSink {
+    gwas_ctx *c;
+    int form;
+    gwas_slab_fn fn;
+    void *user;
+    uint64_t *checksums;
+    int64_t max_checksums;
+    struct Pending {
+        gwas_slab slab;
+        int slot;
+    };
+    std::vector<Pending> inflight;   // issued, not yet consumed, in issue order
+    int64_t issued = 0, consumed = 0;
+    int dslot = 0;                   // device staging buffer of the next slab
+
+    gwas_status init() {
+        gwas_status st = ensure_bstage(c);
+        if (st != GWAS_OK) return st;
+        if (!c->ring.empty()) return GWAS_OK;
+        const int R = c->ring_slots;
         c->ring_bytes = c->bstage_bytes;
         c->ring.assign(R, nullptr);
         c->ring_ev.assign(R, nullptr);
@@ -447,15 +458,10 @@ gwas_status gwas_solve_stream(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, c
             HIP_TRY(hipHostGetDevicePointer(&pd, c->ring[r], 0));
             c->ring_dev.push_back(pd);
         }
+        return GWAS_OK;
     }
 
-    struct Pending {
-        gwas_slab slab;
-        int slot;
-    };
-    std::vector<Pending> inflight;   // issued, not yet consumed, in issue order
-    int64_t issued = 0, consumed = 0;
-    auto consume_one = [&]() -> gwas_status {
+    gwas_status consume_one() {
         Pending pd = inflight.front();
         inflight.erase(inflight.begin());
         HIP_TRY(hipEventSynchronize(c->ring_ev[pd.slot]));
@@ -465,24 +471,37 @@ gwas_status gwas_solve_stream(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, c
         if (fn) fn(user, &pd.slab);
         ++consumed;
         return GWAS_OK;
-    };
+    }
 
-    int dslot = 0;
-    for (int j0 = 0; j0 < tb; j0 += c->tcap) {
-        const int jb = std::min(c->tcap, tb - j0);
-        if ((st = prep_traits(c, j0, jb, Y, y_on_device, h2, form, s)) != GWAS_OK) return st;
-        FusedArgs fa = fused_args(c, jb, form, tb);
-        for (int64_t s0 = 0; s0 < mi; s0 += c->slab, dslot ^= 1) {
-            const int64_t cnt = std::min<int64_t>(c->slab, mi - s0);
+    gwas_status drain() {
+        while (!inflight.empty()) {
+            gwas_status st = consume_one();
+            if (st != GWAS_OK) return st;
+        }
+        return GWAS_OK;
+    }
+
+    // Solve store rows [row0, row0 + count) (SNPs global0 ...) against the trait
+    // sub-block [j0, j0 + fa.tb) prepared in the context, slab by slab into the ring.
+    gwas_status solve_rows(FusedArgs fa, int64_t row0, int64_t global0, int64_t count, int j0, hipStream_t s) {
+        const int R = c->ring_slots;
+        const int p = c->p;
+        const size_t besz = form == GWAS_FORM_F64 ? 8 : 4;
+        const int jb = fa.tb;
+        for (int64_t s0 = 0; s0 < count; s0 += c->slab, dslot ^= 1) {
+            const int64_t cnt = std::min<int64_t>(c->slab, count - s0);
             const int rslot = (int)(issued % R);
-            if ((int64_t)inflight.size() >= R)   // the ring slot is still held: consume the oldest slab
-                if ((st = consume_one()) != GWAS_OK) return st;
+            if ((int64_t)inflight.size() >= R) {   // the ring slot is still held: consume the oldest slab
+                gwas_status st = consume_one();
+                if (st != GWAS_OK) return st;
+            }
             HIP_TRY(hipStreamWaitEvent(s, c->ev_free[dslot], 0));
-            fa.i0 = i0 + s0;
+            fa.i0 = row0 + s0;
             fa.mi = cnt;
             fa.b = c->bstage[dslot];
             fa.ldt = jb;
-            if ((st = launch_fused_timed(c, form, fa, s)) != GWAS_OK) return st;
+            gwas_status st = launch_fused_timed(c, form, fa, s);
+            if (st != GWAS_OK) return st;
             HIP_TRY(hipEventRecord(c->ev_done[dslot], s));
             HIP_TRY(hipStreamWaitEvent(c->side, c->ev_done[dslot], 0));
             const size_t bytes = (size_t)cnt * jb * p * besz;
@@ -494,7 +513,7 @@ gwas_status gwas_solve_stream(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, c
             c->bytes_d2h += (int64_t)bytes;
             Pending pd{};
             pd.slab.index = issued;
-            pd.slab.i0 = i0 + s0;
+            pd.slab.i0 = global0 + s0;
             pd.slab.count = cnt;
             pd.slab.j0 = j0;
             pd.slab.tb = jb;
@@ -505,13 +524,123 @@ gwas_status gwas_solve_stream(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, c
             inflight.push_back(pd);
             ++issued;
         }
+        return GWAS_OK;
     }
-    while (!inflight.empty())
-        if ((st = consume_one()) != GWAS_OK) return st;
-    HIP_TRY(hipEventRecord(c->ev_side, c->side));
-    HIP_TRY(hipStreamWaitEvent(s, c->ev_side, 0));
-    if (n_slabs) *n_slabs = issued;
+
+    // the caller's stream waits for the sink's last copy
+    gwas_status join(hipStream_t s) {
+        HIP_TRY(hipEventRecord(c->ev_side, c->side));
+        HIP_TRY(hipStreamWaitEvent(s, c->ev_side, 0));
+        return GWAS_OK;
+    }
+};
+
+}  // namespace
+
+gwas_status gwas_solve_stream(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, const double *Y,
+                              int32_t y_on_device, const double *h2, int32_t form, gwas_slab_fn fn,
+                              void *user, uint64_t *checksums, int64_t max_checksums, int64_t *n_slabs,
+                              void *stream) {
+    last_error().clear();
+    gwas_status st = check_solve(c, i0, mi, tb, Y, y_on_device, h2, form);
+    if (st != GWAS_OK) return st;
+    if (n_slabs) *n_slabs = 0;
+    if (mi == 0) return GWAS_OK;
+    HIP_TRY(hipSetDevice(c->dev));
+    hipStream_t s = (hipStream_t)stream;
+    RingSink sink{c, form, fn, user, checksums, max_checksums};
+    if ((st = sink.init()) != GWAS_OK) return st;
+    for (int j0 = 0; j0 < tb; j0 += c->tcap) {
+        const int jb = std::min(c->tcap, tb - j0);
+        if ((st = prep_traits(c, j0, jb, Y, y_on_device, h2, form, s)) != GWAS_OK) return st;
+        if ((st = sink.solve_rows(fused_args(c, jb, form, tb), i0, i0, mi, j0, s)) != GWAS_OK) return st;
+    }
+    if ((st = sink.drain()) != GWAS_OK) return st;
+    if ((st = sink.join(s)) != GWAS_OK) return st;
+    if (n_slabs) *n_slabs = sink.issued;
     c->problems += mi * (int64_t)tb;
+    return GWAS_OK;
+}
+
+gwas_status gwas_solve_snp_stream(gwas_ctx *c, const void *X_R, int32_t dtype, int64_t m, int32_t tb,
+                                  const double *Y, int32_t y_on_device, const double *h2, int32_t form,
+                                  gwas_slab_fn fn, void *user, uint64_t *checksums, int64_t max_checksums,
+                                  int64_t *n_slabs, void *stream) {
+    last_error().clear();
+    if (!c) return fail(GWAS_EINVAL, "ctx is NULL");
+    if (m < 0) return fail(GWAS_EINVAL, "m = %lld is negative", (long long)m);
+    if (dtype != GWAS_DT_F64 && dtype != GWAS_DT_F32 && dtype != GWAS_DT_U8)
+        return fail(GWAS_EINVAL, "unknown dtype %d", dtype);
+    if (c->m_cap < 2) return fail(GWAS_EINVAL, "m_capacity must be at least 2 (the store holds two blocks)");
+    gwas_status st = check_solve(c, 0, 0, tb, Y, y_on_device, h2, form);
+    if (st != GWAS_OK) return st;
+    if (n_slabs) *n_slabs = 0;
+    if (m == 0) return GWAS_OK;
+    if (!X_R) return fail(GWAS_EINVAL, "X_R is NULL");
+    HIP_TRY(hipSetDevice(c->dev));
+    hipStream_t s = (hipStream_t)stream;
+    const size_t esz = dtype == GWAS_DT_F64 ? 8 : (dtype == GWAS_DT_F32 ? 4 : 1);
+    const int64_t B = c->m_cap / 2;   // SNPs per block; block k uses store half k % 2
+    // device staging of the raw SNP blocks (two, so the next block's copy can start
+    // while this one rotates), the stream that copies and rotates, and its events
+    const size_t in_bytes = (size_t)B * c->n * esz;
+    if (c->xin_bytes < in_bytes) {
+        for (int h = 0; h < 2; ++h) {
+            if (c->xin[h]) HIP_TRY(hipFree(c->xin[h]));
+            c->xin[h] = nullptr;
+        }
+        c->xin_bytes = 0;
+        for (int h = 0; h < 2; ++h) {
+            hipError_t e = hipMalloc(&c->xin[h], in_bytes);
+            if (e != hipSuccess) return fail(GWAS_ENOMEM, "SNP block staging (%zu bytes): %s", in_bytes,
+                                             hipGetErrorString(e));
+        }
+        c->xin_bytes = in_bytes;
+    }
+    if (!c->aux) {
+        HIP_TRY(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+        for (int h = 0; h < 2; ++h) {
+            HIP_TRY(hipEventCreateWithFlags(&c->ev_rot[h], hipEventDisableTiming));
+            HIP_TRY(hipEventCreateWithFlags(&c->ev_half[h], hipEventDisableTiming));
+        }
+    }
+    RingSink sink{c, form, fn, user, checksums, max_checksums};
+    if ((st = sink.init()) != GWAS_OK) return st;
+    // the store halves start free once the caller's stream has reached this call
+    for (int h = 0; h < 2; ++h) HIP_TRY(hipEventRecord(c->ev_half[h], s));
+    const bool one_trait_block = tb <= c->tcap;
+    if (one_trait_block && (st = prep_traits(c, 0, tb, Y, y_on_device, h2, form, s)) != GWAS_OK) return st;
+    const int64_t nblk = (m + B - 1) / B;
+    std::pair<hipEvent_t, hipEvent_t> ev{};
+    for (int64_t k = 0; k < nblk; ++k) {
+        const int h = (int)(k % 2);
+        const int64_t g0 = k * B, cnt = std::min(B, m - g0);
+        // copy + rotate block k into store half h once its previous block is solved
+        HIP_TRY(hipStreamWaitEvent(c->aux, c->ev_half[h], 0));
+        HIP_TRY(hipMemcpyAsync(c->xin[h], (const uint8_t *)X_R + (size_t)g0 * c->n * esz, (size_t)cnt * c->n * esz,
+                               hipMemcpyDefault, c->aux));
+        c->bytes_h2d += (int64_t)cnt * c->n * (int64_t)esz;
+        RotOut ro{c->xr64, c->xr32, c->xrbf, c->m_rows, (int64_t)h * B, c->n_pad};
+        HIP_TRY(timed_begin(c, c->aux, ev));
+        HIP_TRY(launch_rotate(c->xin[h], dtype, cnt, c->n, c->n, c->Z, c->n_pad, ro, c->aux));
+        HIP_TRY(timed_end(c, c->aux, ev, c->t_rot));
+        HIP_TRY(hipEventRecord(c->ev_rot[h], c->aux));
+        c->snps_rotated += cnt;
+        // solve block k from half h on the caller's stream
+        HIP_TRY(hipStreamWaitEvent(s, c->ev_rot[h], 0));
+        for (int j0 = 0; j0 < tb; j0 += c->tcap) {
+            const int jb = std::min(c->tcap, tb - j0);
+            if (!one_trait_block && (st = prep_traits(c, j0, jb, Y, y_on_device, h2, form, s)) != GWAS_OK)
+                return st;
+            if ((st = sink.solve_rows(fused_args(c, jb, form, tb), (int64_t)h * B, g0, cnt, j0, s)) != GWAS_OK)
+                return st;
+        }
+        HIP_TRY(hipEventRecord(c->ev_half[h], s));
+    }
+    if ((st = sink.drain()) != GWAS_OK) return st;
+    if ((st = sink.join(s)) != GWAS_OK) return st;
+    if (n_slabs) *n_slabs = sink.issued;
+    c->problems += m * (int64_t)tb;
     return GWAS_OK;
 }
 

@@ -109,6 +109,14 @@ struct gwas_ctx {
     hipEvent_t ev_free[2] = {nullptr, nullptr};   // slab copied out
     hipEvent_t ev_side = nullptr;
 
+    // genotype stream (gwas_solve_snp_stream): raw SNP block staging, the stream
+    // that copies and rotates blocks, block rotated / store half free events
+    void *xin[2] = {nullptr, nullptr};
+    size_t xin_bytes = 0;
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_rot[2] = {nullptr, nullptr};
+    hipEvent_t ev_half[2] = {nullptr, nullptr};
+
     // streamed sink: pinned host ring
     int ring_slots = 4, host_threads = 8;
     std::vector<void *> ring;

@@ -107,6 +107,9 @@ def load():
     lib.gwas_solve_stream.argtypes = [vp, i64, i64, i32, vp, i32, vp, i32, SLAB_FN, vp,
                                       ctypes.POINTER(ctypes.c_uint64), i64, ctypes.POINTER(i64), vp]
     lib.gwas_solve_stream.restype = i32
+    lib.gwas_solve_snp_stream.argtypes = [vp, vp, i32, i64, i32, vp, i32, vp, i32, SLAB_FN, vp,
+                                          ctypes.POINTER(ctypes.c_uint64), i64, ctypes.POINTER(i64), vp]
+    lib.gwas_solve_snp_stream.restype = i32
     lib.gwas_checksum.argtypes = [vp, i64]
     lib.gwas_checksum.restype = ctypes.c_uint64
     lib.gwas_clock.argtypes = []
@@ -288,24 +291,8 @@ class Cohort:
         self._keep = (ykeep, h2)
         return out
 
-    def solve_stream(self, y, h2, form: str = "f32", i0: int = 0, m: int | None = None,
-                     on_slab=None, stream=None, max_slabs: int = 1 << 20):
-        """Streamed solve: b arrives slab by slab in pinned host memory.
-
-        on_slab(slab_info: dict, b: numpy view) is called for each slab on the
-        calling thread; the view is valid only during the call. Returns the
-        list of slab checksums (see gwas_checksum).
-        """
-        lib = load()
-        f = FORMS[form]
-        m = self.m_capacity - i0 if m is None else int(m)
-        t = int(y.shape[0])
-        h2 = np.ascontiguousarray(h2, dtype=np.float64)
-        if h2.shape != (t,):
-            raise ValueError("h2 needs one value per trait")
-        yp, ydev, ykeep = _ptr(y if _is_device(y) else np.ascontiguousarray(y, dtype=np.float64))
-        dt = np.float64 if f == FORM_F64 else np.float32
-        errors = []
+    def _slab_callback(self, form, on_slab, errors):
+        dt = np.float64 if FORMS[form] == FORM_F64 else np.float32
 
         def cb(_user, sp):
             if on_slab is None:
@@ -320,7 +307,30 @@ class Cohort:
             except Exception as e:       # never propagate through the C frame
                 errors.append(e)
 
-        fn = SLAB_FN(cb)
+        return SLAB_FN(cb)
+
+    def _traits(self, y, h2):
+        t = int(y.shape[0])
+        h2 = np.ascontiguousarray(h2, dtype=np.float64)
+        if h2.shape != (t,):
+            raise ValueError("h2 needs one value per trait")
+        yp, ydev, ykeep = _ptr(y if _is_device(y) else np.ascontiguousarray(y, dtype=np.float64))
+        return t, h2, yp, ydev, ykeep
+
+    def solve_stream(self, y, h2, form: str = "f32", i0: int = 0, m: int | None = None,
+                     on_slab=None, stream=None, max_slabs: int = 1 << 20):
+        """Streamed solve: b arrives slab by slab in pinned host memory.
+
+        on_slab(slab_info: dict, b: numpy view) is called for each slab on the
+        calling thread; the view is valid only during the call. Returns the
+        list of slab checksums (see gwas_checksum).
+        """
+        lib = load()
+        f = FORMS[form]
+        m = self.m_capacity - i0 if m is None else int(m)
+        t, h2, yp, ydev, ykeep = self._traits(y, h2)
+        errors = []
+        fn = self._slab_callback(form, on_slab, errors)
         sums = (ctypes.c_uint64 * max_slabs)()
         n = ctypes.c_int64(0)
         _check(lib.gwas_solve_stream(self._h, int(i0), m, t, yp, ydev, h2.ctypes.data, f, fn, None,
@@ -328,6 +338,30 @@ class Cohort:
         if errors:
             raise errors[0]
         del ykeep
+        return [int(sums[k]) for k in range(min(n.value, max_slabs))]
+
+    def solve_snp_stream(self, xr, y, h2, form: str = "f32", on_slab=None, stream=None,
+                         max_slabs: int = 1 << 20):
+        """Genotype stream: SNP columns xr [m][n] (uint8, float32 or float64; numpy, or a
+        pinned or device torch tensor) are copied, rotated and solved block by block
+        through the resident store (m may exceed m_capacity); b arrives as in
+        solve_stream, slab i0 being the SNP's row in xr. Returns the slab checksums."""
+        lib = load()
+        f = FORMS[form]
+        xp, _xdev, xkeep = _ptr(xr)
+        m = int(xr.shape[0])
+        if m and int(xr.shape[1]) != self.n:
+            raise ValueError("SNP columns must be [m][n]")
+        t, h2, yp, ydev, ykeep = self._traits(y, h2)
+        errors = []
+        fn = self._slab_callback(form, on_slab, errors)
+        sums = (ctypes.c_uint64 * max_slabs)()
+        n = ctypes.c_int64(0)
+        _check(lib.gwas_solve_snp_stream(self._h, xp, _dtype_code(xr), m, t, yp, ydev, h2.ctypes.data, f, fn,
+                                         None, sums, max_slabs, ctypes.byref(n), _stream_ptr(stream)))
+        if errors:
+            raise errors[0]
+        del ykeep, xkeep
         return [int(sums[k]) for k in range(min(n.value, max_slabs))]
 
     def copy_rotated(self, i0: int, m: int, form: str = "f64"):
