@@ -612,13 +612,15 @@ gwas_status gwas_solve_snp_stream(gwas_ctx *c, const void *X_R, int32_t dtype, i
     if (one_trait_block && (st = prep_traits(c, 0, tb, Y, y_on_device, h2, form, s)) != GWAS_OK) return st;
     const int64_t nblk = (m + B - 1) / B;
     std::pair<hipEvent_t, hipEvent_t> ev{};
-    for (int64_t k = 0; k < nblk; ++k) {
+    // copy + rotate block k into store half k % 2 once the block before it in
+    // that half is solved (enqueued two blocks ahead, so it runs while the
+    // previous block is solved and its b leaves)
+    auto load_block = [&](int64_t k) -> gwas_status {
         const int h = (int)(k % 2);
         const int64_t g0 = k * B, cnt = std::min(B, m - g0);
-        // copy + rotate block k into store half h once its previous block is solved
         HIP_TRY(hipStreamWaitEvent(c->aux, c->ev_half[h], 0));
-        HIP_TRY(hipMemcpyAsync(c->xin[h], (const uint8_t *)X_R + (size_t)g0 * c->n * esz, (size_t)cnt * c->n * esz,
-                               hipMemcpyDefault, c->aux));
+        HIP_TRY(hipMemcpyAsync(c->xin[h], (const uint8_t *)X_R + (size_t)g0 * c->n * esz,
+                               (size_t)cnt * c->n * esz, hipMemcpyDefault, c->aux));
         c->bytes_h2d += (int64_t)cnt * c->n * (int64_t)esz;
         RotOut ro{c->xr64, c->xr32, c->xrbf, c->m_rows, (int64_t)h * B, c->n_pad};
         HIP_TRY(timed_begin(c, c->aux, ev));
@@ -626,6 +628,13 @@ gwas_status gwas_solve_snp_stream(gwas_ctx *c, const void *X_R, int32_t dtype, i
         HIP_TRY(timed_end(c, c->aux, ev, c->t_rot));
         HIP_TRY(hipEventRecord(c->ev_rot[h], c->aux));
         c->snps_rotated += cnt;
+        return GWAS_OK;
+    };
+    for (int64_t k = 0; k < std::min<int64_t>(2, nblk); ++k)
+        if ((st = load_block(k)) != GWAS_OK) return st;
+    for (int64_t k = 0; k < nblk; ++k) {
+        const int h = (int)(k % 2);
+        const int64_t g0 = k * B, cnt = std::min(B, m - g0);
         // solve block k from half h on the caller's stream
         HIP_TRY(hipStreamWaitEvent(s, c->ev_rot[h], 0));
         for (int j0 = 0; j0 < tb; j0 += c->tcap) {
@@ -636,6 +645,7 @@ gwas_status gwas_solve_snp_stream(gwas_ctx *c, const void *X_R, int32_t dtype, i
                 return st;
         }
         HIP_TRY(hipEventRecord(c->ev_half[h], s));
+        if (k + 2 < nblk && (st = load_block(k + 2)) != GWAS_OK) return st;
     }
     if ((st = sink.drain()) != GWAS_OK) return st;
     if ((st = sink.join(s)) != GWAS_OK) return st;

@@ -53,9 +53,10 @@ class Workload:
         return self.m * self.t
 
 
-# The six workloads: tiny FP64 check; paper shape (n=1000, p=4) at m=1e5 and
-# m=1e6; a streamed 1e6 x 1e4 grid; a resident 1e6-SNP cohort for serving; and
-# the single-trait case (t = 1) of the same cohort shape.
+# The seven workloads: tiny FP64 check; paper shape (n=1000, p=4) at m=1e5 and
+# m=1e6; a streamed 1e6 x 1e4 grid; a resident 1e6-SNP cohort for serving; the
+# single-trait case (t = 1) of the same cohort shape; and 4e6 SNPs streamed
+# from host memory through a 2^20-SNP store.
 WORKLOADS = {
     "tiny": Workload("tiny", 0, n=128, p=4, m=512, t=8, k=1000),
     "paper_m1e5": Workload("paper_m1e5", 1, n=1000, p=4, m=100_000, t=1000, k=5000),
@@ -63,6 +64,7 @@ WORKLOADS = {
     "stream_m1e6_t1e4": Workload("stream_m1e6_t1e4", 3, n=1000, p=4, m=1_000_000, t=10_000, k=5000),
     "serve_m1e6": Workload("serve_m1e6", 4, n=1000, p=8, m=1_000_000, t=512, k=5000),
     "single_trait_m1e6": Workload("single_trait_m1e6", 5, n=1000, p=4, m=1_000_000, t=1, k=5000),
+    "snp_stream_m4e6_t100": Workload("snp_stream_m4e6_t100", 6, n=1000, p=4, m=4_000_000, t=100, k=5000),
 }
 
 
