@@ -294,3 +294,27 @@ def test_streamed_slabs_match_resident_b_and_checksums(form, torch_cuda):
     from paper_1210_7683_amd import gwas
     assert gwas.checksum(dev[:160, :16]) == _checksum_numpy(dev[:160, :16]) == sums[0]
     c.close()
+
+
+def test_large_n_sampled_against_oracle(torch_cuda):
+    """n = 4096 samples (a K loop four times the paper's, 128 FP64-fold windows in
+    the FP32 form), m = 1500, t = 8, every form; 300 sampled problems against the
+    oracle (one dense Cholesky of each M_j)."""
+    torch = torch_cuda
+    n, p, m, t = 4096, 4, 1500, 8
+    phi, xl, xr, y, h2 = synth.small(n, p, m, t, seed=4096, k=2 * n)
+    rng = np.random.default_rng(1)
+    ii = rng.choice(m, size=300, replace=False)
+    jj = rng.integers(0, t, size=300)
+    ref = oracle.gls(phi, xl, xr[ii], y, h2, trait=jj)
+    w, z = np.linalg.eigh(phi)
+    from paper_1210_7683_amd import gwas
+    with gwas.Cohort(z, w, xl, m) as c:
+        c.rotate(0, torch.from_numpy(xr).cuda())
+        for form in FORMS:
+            b = c.solve(y, h2, form=form)
+            got = b[torch.from_numpy(ii).cuda(), torch.from_numpy(jj).cuda()].cpu().numpy()
+            e = rel_err(got, ref)
+            print("n=%d %s: relative max %.3e, median %.3e" % (n, form, e.max(), np.median(e)))
+            assert bool(torch.isfinite(b).all())
+            assert e.max() <= TOL[form]
