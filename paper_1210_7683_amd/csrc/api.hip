@@ -194,7 +194,8 @@ gwas_status gwas_setup(gwas_ctx **out, int32_t n, int32_t p, const double *Z, co
             TRY(dalloc(c, &c->panels[f], elt_size(f) * planes * c->tcap * np));
         }
     TRY(dalloc(c, &c->fac, sizeof(double) * (size_t)c->tcap * fac_stride(p)));
-    TRY(dalloc(c, &c->counters, sizeof(unsigned long long) * 4));
+    // [0..3] statistics, [4..7] the 8 tile counters of persistent launches
+    TRY(dalloc(c, &c->counters, sizeof(unsigned long long) * 8));
     c->stage_bytes = (size_t)64 << 20;
     TRY(dalloc(c, &c->stage, c->stage_bytes));
 
@@ -336,6 +337,7 @@ FusedArgs fused_args(gwas_ctx *c, int jb, int32_t form, int tb_call) {
     fa.p = c->p;
     fa.rank_rtol = kRankRtol[form];
     fa.non_spd = c->counters;
+    fa.tile_counters = (unsigned *)(c->counters + 4);
     fa.f32_flush = form == GWAS_FORM_F32 ? c->f32_flush : 0;
     fa.small_t = use_dot_kernel(form, c->p, tb_call, c->n_pad);
     return fa;

@@ -98,7 +98,7 @@ struct gwas_ctx {
     double *h2 = nullptr;    // [tcap]
     void *panels[3] = {nullptr, nullptr, nullptr};  // per form
     double *fac = nullptr;   // [tcap][fac_stride]
-    unsigned long long *counters = nullptr;  // [0] non-SPD problems
+    unsigned long long *counters = nullptr;  // [0] non-SPD problems; [4..7] persistent tile counters
 
     void *stage = nullptr;   // rotation staging for host SNP blocks
     size_t stage_bytes = 0;

@@ -29,10 +29,11 @@
 
 namespace gw {
 
-template <int WM_, int WN_, int FM_, int FN_, int KB_, bool PIPE_ = false>
+template <int WM_, int WN_, int FM_, int FN_, int KB_, bool PIPE_ = false, bool PERSIST_ = false>
 struct DmaTile {
     static constexpr int WM = WM_, WN = WN_, FM = FM_, FN = FN_, KB = KB_;
-    static constexpr bool PIPE = PIPE_;
+    static constexpr bool PIPE = PIPE_;       // two LDS buffers
+    static constexpr bool PERSIST = PERSIST_; // persistent workgroups, one per CU
 };
 
 template <int FORM, int P, class T>
@@ -301,12 +302,54 @@ __global__ __launch_bounds__((DmaCfg<FORM, P, T>::NT)) void fused_dma_kernel(Fus
     dma_tile<FORM, P, FLUSH, T>(a, tile_order(blockIdx.x, ntm, ntn), lds);
 }
 
+// Persistent variant: one workgroup per CU; workgroup b (on XCD b mod 8) takes
+// the tiles x + 8 l of the order above (x = b mod 8) from its XCD's counter
+// until they run out, so each XCD still covers its eighth of the trait tiles.
+// Every workgroup reaches the exit once its counter passes the tile count.
+template <int FORM, int P, bool FLUSH, class T>
+__global__ __launch_bounds__((DmaCfg<FORM, P, T>::NT)) void fused_dma_persistent_kernel(FusedArgs a) {
+    using C = DmaCfg<FORM, P, T>;
+    extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
+    __shared__ unsigned next;
+    const int ntn = (a.tb + C::TN - 1) / C::TN;
+    const int64_t ntm = (a.mi + C::TM - 1) / C::TM;
+    const int64_t total = ntm * ntn;
+    const int x = blockIdx.x % 8;
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(a.tile_counters + x, 1u);
+        __syncthreads();
+        const int64_t b = (int64_t)next * 8 + x;
+        __syncthreads();   // every thread has read `next` before it is overwritten
+        if (b >= total) return;
+        dma_tile<FORM, P, FLUSH, T>(a, tile_order(b, ntm, ntn), lds);
+    }
+}
+
 template <int FORM, int P, bool FLUSH, class T>
 hipError_t launch_dma_t(const FusedArgs &a, hipStream_t s) {
     using C = DmaCfg<FORM, P, T>;
     const int64_t tiles = ((a.mi + C::TM - 1) / C::TM) * ((a.tb + C::TN - 1) / C::TN);
     if (a.mi <= 0 || a.tb <= 0) return hipSuccess;
     if ((a.n_pad * C::ESZ) % (C::KB * 64)) return hipErrorInvalidValue;
+    if constexpr (T::PERSIST) {
+        if (!a.tile_counters) return hipErrorInvalidValue;
+        static bool attr_set = false;   // per instantiation
+        if (C::LDS > 65536 && !attr_set) {
+            hipError_t e = hipFuncSetAttribute((const void *)fused_dma_persistent_kernel<FORM, P, FLUSH, T>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS);
+            if (e != hipSuccess) return e;
+            attr_set = true;
+        }
+        int dev = 0, cus = 256;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess) e = hipMemsetAsync(a.tile_counters, 0, 8 * sizeof(unsigned), s);
+        if (e != hipSuccess) return e;
+        const int64_t grid = std::max<int64_t>(8, std::min<int64_t>(cus, (tiles + 7) / 8 * 8));
+        hipLaunchKernelGGL((fused_dma_persistent_kernel<FORM, P, FLUSH, T>), dim3((unsigned)grid), dim3(C::NT),
+                           C::LDS, s, a);
+        return hipGetLastError();
+    }
     if (C::LDS > 65536) {
         static bool attr_set = false;   // per instantiation
         if (!attr_set) {
@@ -324,7 +367,9 @@ hipError_t launch_dma_t(const FusedArgs &a, hipStream_t s) {
 // (m = 1e5, t = 1000): one 16x16 block of problems per wave for FP64 and FP32,
 // 32x32 per wave for split BF16 (more reuse of its larger operands). FP32 and
 // split BF16 run two LDS buffers (PIPE); for FP64 the single buffer with a
-// smaller LDS footprint measured faster. Larger p narrows the split-BF16 tile,
+// smaller LDS footprint measured faster. Persistent workgroups measured 2-6%
+// faster than one workgroup per tile for split BF16 at p <= 4 (varying
+// between runs) and no faster for FP32 and FP64. Larger p narrows the split-BF16 tile,
 // and from p = 10 (FP32: 12) the workgroup drops to 4 waves, one per SIMD, so
 // a wave may hold up to 512 registers of p + 1 accumulator sets and fragments.
 template <int FORM, int P>
@@ -332,7 +377,7 @@ struct DmaDefault {
     using F64T = typename std::conditional<(P <= 9), DmaTile<4, 2, 1, 1, 1>, DmaTile<4, 1, 1, 1, 1>>::type;
     using F32T = typename std::conditional<(P <= 11), DmaTile<8, 1, 1, 1, 2, true>,
                                            DmaTile<4, 1, 1, 1, 2, true>>::type;
-    using BF16T = typename std::conditional<(P <= 4), DmaTile<8, 1, 2, 2, 1, true>,
+    using BF16T = typename std::conditional<(P <= 4), DmaTile<8, 1, 2, 2, 1, true, true>,
                   typename std::conditional<(P <= 9), DmaTile<8, 1, 2, 1, 1, true>,
                                             DmaTile<4, 1, 1, 1, 1, true>>::type>::type;
     using type = typename std::conditional<FORM == GWAS_FORM_F64, F64T,

@@ -120,6 +120,7 @@ struct FusedArgs {
     unsigned long long *non_spd;
     int f32_flush;
     int small_t;            // nonzero: the call has at most kSmallT traits (dot-product kernel)
+    unsigned *tile_counters;  // 8 device words for persistent launches (zeroed by the launcher)
 };
 hipError_t launch_fused(int form, const FusedArgs &a, hipStream_t s);
 
