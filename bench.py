@@ -30,7 +30,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # MI355X published dense peaks
-PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0}
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}
+DEFAULT_FORMS = "f32,f64,bf16x3,bf16x6"
+# BF16 MFMA products executed per algorithmic product
+MFMA_MULT = {"f64": 1, "f32": 1, "bf16x3": 3, "bf16x6": 6}
 HBM_GBPS = 8000.0
 
 
@@ -336,7 +339,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="paper_m1e5")
-    ap.add_argument("--forms", default="f32,f64,bf16x3", help="headline form first")
+    ap.add_argument("--forms", default=DEFAULT_FORMS, help="headline form first")
     ap.add_argument("--f32-flush", type=int, default=None,
                     help="FP32 form: FP64 fold interval in chunks of 16 samples (library default 2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -364,19 +367,19 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     if args.workload.startswith("stream"):
-        if args.forms == "f32,f64,bf16x3":
+        if args.forms == DEFAULT_FORMS:
             args.forms = "bf16x3"
         return stream_bench(args)
     if args.workload.startswith("snp_stream"):
-        if args.forms == "f32,f64,bf16x3":
+        if args.forms == DEFAULT_FORMS:
             args.forms = "f32"
         return snp_stream_bench(args)
     if args.workload.startswith("single_trait"):
-        if args.forms == "f32,f64,bf16x3":
+        if args.forms == DEFAULT_FORMS:
             args.forms = "f32,f64"
         return single_trait_bench(args)
     if args.workload.startswith("serve"):
-        if args.forms == "f32,f64,bf16x3":
+        if args.forms == DEFAULT_FORMS:
             args.forms = "f32"
         return serve_bench(args)
     forms = args.forms.split(",")
@@ -438,7 +441,7 @@ def main():
         st = cohort.stats()
         fused_ms = st["fused_ms"] / max(1, st["fused_launches"])
         rot_ms = st["rotate_ms"] / max(1, st["rotate_launches"])
-        mult = 3 if form == "bf16x3" else 1          # three BF16 products per pair
+        mult = MFMA_MULT[form]
         achieved = mult * flops_gls * problems / (fused_ms * 1e-3) / 1e12
         results[form] = {
             "gls_per_s": problems / (ms * 1e-3),
@@ -464,7 +467,7 @@ def main():
 
     head = forms[0]
     r = results[head]
-    mult = 3 if head == "bf16x3" else 1
+    mult = MFMA_MULT[head]
     line = {
         "metric": "GLS problems solved/s + MFMA % of peak, FP64 vs FP32 vs split-BF16; p99",
         "value": r["gls_per_s"],
@@ -476,7 +479,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f32": "f32", "f64": "f64", "bf16x3": "bf16x3"}[head],
+        "dtype": head,
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "p": w.p, "m": w.m, "t": w.t,
                    "form": head, "step": "rotate all SNPs + solve the full grid, b in HBM"},

@@ -58,6 +58,10 @@ typedef int32_t gwas_status;
 #define GWAS_FORM_F32 1    /* FP32 operands, FP32 MFMA accumulation; b in FP32          */
 #define GWAS_FORM_BF16X3 2 /* split BF16 operands x = hi + lo, hi*hi + hi*lo + lo*hi,
                               FP32 MFMA accumulation; b in FP32                          */
+#define GWAS_FORM_BF16X6 3 /* split BF16 in three pieces x = hi + mid + lo (the FP32 value
+                              exactly), six products hi*hi + hi*mid + mid*hi + hi*lo +
+                              lo*hi + mid*mid on the BF16 MFMAs, FP32 accumulation added
+                              to FP64 sums every 32 samples; b in FP32                   */
 #define GWAS_FORM_BIT(f) (1u << (f))
 
 typedef struct gwas_ctx gwas_ctx;
@@ -65,7 +69,7 @@ typedef struct gwas_ctx gwas_ctx;
 typedef struct gwas_options {
     int64_t m_capacity;  /* SNPs the cohort holds (> 0)                                 */
     uint32_t forms;      /* OR of GWAS_FORM_BIT(): rotated SNP copies kept resident;
-                            0 means all three                                         */
+                            0 means FP64, FP32 and BF16X3                             */
     int32_t device;      /* HIP device ordinal; -1: the current device                 */
     int32_t max_traits;  /* traits handled per internal trait sub-block; 0: 1024       */
     int32_t slab_snps;   /* SNPs per D2H slab when b goes to the host; 0: 16384        */
@@ -278,7 +282,8 @@ typedef struct gwas_server gwas_server;
 typedef struct gwas_server_options {
     int64_t hbm_budget;  /* device bytes admitted requests may hold at once; 0: 8 GiB      */
     int32_t max_slots;   /* requests in flight at once, 1..32; 0: 8                        */
-    int32_t form;        /* GWAS_FORM_* used for every request (must be resident)          */
+    int32_t form;        /* GWAS_FORM_F64, _F32 or _BF16X3, used for every request (must be
+                            resident); GWAS_FORM_BF16X6 is not served: GWAS_EINVAL       */
     int32_t item_problems; /* target problems (SNPs x traits) per work item; 0: 4194304    */
     int32_t max_traits;  /* largest request trait count accepted; 0: 1024                  */
     int32_t ring_slots;  /* pinned host ring slots; 0: 2 x max_slots                       */

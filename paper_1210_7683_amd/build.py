@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgwas.so")
 OBJDIR = os.path.join(ROOT, "_build", "gwas")
 SOURCES = ["api.hip", "server.hip", "serve.hip", "copy.hip", "rotate.hip", "prep.hip", "fused_f64.hip", "fused_f32.hip",
-           "fused_bf16.hip"]
+           "fused_bf16.hip", "fused_bf16x6.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

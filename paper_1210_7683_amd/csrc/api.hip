@@ -79,7 +79,7 @@ void release(gwas_ctx *c) {
             hipEventDestroy(ev.second);
         }
     void *ptrs[] = {c->Z, c->w, c->xlt, c->xr64, c->xr32, c->xrbf, c->y_in, c->yt, c->h2,
-                    c->panels[0], c->panels[1], c->panels[2], c->fac, c->counters, c->stage,
+                    c->panels[0], c->panels[1], c->panels[2], c->panels[3], c->xrbf3, c->fac, c->counters, c->stage,
                     c->bstage[0], c->bstage[1], c->xin[0], c->xin[1]};
     for (void *p : ptrs)
         if (p) hipFree(p);
@@ -107,6 +107,9 @@ bool all_finite(const double *v, size_t count) {
 
 size_t elt_size(int form) { return form == GWAS_FORM_F64 ? 8 : (form == GWAS_FORM_F32 ? 4 : 2); }
 
+// planes per trait panel (and per SNP row) of a form: the BF16 pieces
+int panel_planes(int form) { return form == GWAS_FORM_BF16X3 ? 2 : (form == GWAS_FORM_BF16X6 ? 3 : 1); }
+
 }  // namespace
 
 namespace gw {
@@ -115,6 +118,7 @@ hipError_t launch_fused(int form, const FusedArgs &a, hipStream_t s) {
     case GWAS_FORM_F64: return launch_fused_f64(a, s);
     case GWAS_FORM_F32: return launch_fused_f32(a, s);
     case GWAS_FORM_BF16X3: return launch_fused_bf16(a, s);
+    case GWAS_FORM_BF16X6: return launch_fused_bf16x6(a, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -151,7 +155,7 @@ gwas_status gwas_setup(gwas_ctx **out, int32_t n, int32_t p, const double *Z, co
     if (opt->f32_flush != 0 && opt->f32_flush != 2)
         return fail(GWAS_EINVAL, "f32_flush = %d: 0 (no fold) or 2 (fold every 32 samples)", opt->f32_flush);
     const uint32_t forms = opt->forms ? opt->forms : 7u;
-    if (forms & ~7u) return fail(GWAS_EINVAL, "unknown form bits 0x%x", forms);
+    if (forms & ~15u) return fail(GWAS_EINVAL, "unknown form bits 0x%x", forms);
     if (!all_finite(Z, (size_t)n * n) || !all_finite(w, n) || !all_finite(X_L, (size_t)n * (p - 1)))
         return fail(GWAS_EINVAL, "non-finite value in Z, w or X_L");
 
@@ -185,12 +189,13 @@ gwas_status gwas_setup(gwas_ctx **out, int32_t n, int32_t p, const double *Z, co
     if (forms & GWAS_FORM_BIT(GWAS_FORM_F64)) TRY(dalloc(c, &c->xr64, sizeof(double) * plane));
     if (forms & GWAS_FORM_BIT(GWAS_FORM_F32)) TRY(dalloc(c, &c->xr32, sizeof(float) * plane));
     if (forms & GWAS_FORM_BIT(GWAS_FORM_BF16X3)) TRY(dalloc(c, &c->xrbf, sizeof(uint16_t) * 2 * plane));
+    if (forms & GWAS_FORM_BIT(GWAS_FORM_BF16X6)) TRY(dalloc(c, &c->xrbf3, sizeof(uint16_t) * 3 * plane));
     TRY(dalloc(c, &c->y_in, sizeof(double) * (size_t)c->tcap * n));
     TRY(dalloc(c, &c->yt, sizeof(double) * (size_t)c->tcap * np));
     TRY(dalloc(c, &c->h2, sizeof(double) * (size_t)c->tcap));
-    for (int f = 0; f < 3; ++f)
+    for (int f = 0; f < 4; ++f)
         if (forms & GWAS_FORM_BIT(f)) {
-            const size_t planes = (f == GWAS_FORM_BF16X3) ? 2 * (size_t)(p + 1) : (size_t)(p + 1);
+            const size_t planes = (size_t)panel_planes(f) * (p + 1);
             TRY(dalloc(c, &c->panels[f], elt_size(f) * planes * c->tcap * np));
         }
     TRY(dalloc(c, &c->fac, sizeof(double) * (size_t)c->tcap * fac_stride(p)));
@@ -214,7 +219,7 @@ gwas_status gwas_setup(gwas_ctx **out, int32_t n, int32_t p, const double *Z, co
         if (e != hipSuccess) { release(c); return fail(GWAS_EHIP, "upload w: %s", hipGetErrorString(e)); }
         e = hipMemcpy(c->stage, X_L, sizeof(double) * (size_t)n * (p - 1), hipMemcpyHostToDevice);
         if (e != hipSuccess) { release(c); return fail(GWAS_EHIP, "upload X_L: %s", hipGetErrorString(e)); }
-        RotOut ro{c->xlt, nullptr, nullptr, 0, 0, np};
+        RotOut ro{c->xlt, nullptr, nullptr, nullptr, 0, 0, np};
         e = launch_rotate(c->stage, GWAS_DT_F64, p - 1, n, n, c->Z, np, ro, nullptr);
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e != hipSuccess) { release(c); return fail(GWAS_EHIP, "rotate X_L: %s", hipGetErrorString(e)); }
@@ -255,7 +260,7 @@ gwas_status gwas_rotate(gwas_ctx *c, int64_t m0, int64_t mb, const void *X, int3
     HIP_TRY(hipSetDevice(c->dev));
     hipStream_t s = (hipStream_t)stream;
     const size_t esz = dtype == GWAS_DT_F64 ? 8 : (dtype == GWAS_DT_F32 ? 4 : 1);
-    RotOut ro{c->xr64, c->xr32, c->xrbf, c->m_rows, 0, c->n_pad};
+    RotOut ro{c->xr64, c->xr32, c->xrbf, c->xrbf3, c->m_rows, 0, c->n_pad};
     std::pair<hipEvent_t, hipEvent_t> ev{};
     if (on_device) {
         ro.row0 = m0;
@@ -287,7 +292,7 @@ namespace {
 gwas_status check_solve(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, const double *Y, int32_t y_on_device,
                         const double *h2, int32_t form) {
     if (!c) return fail(GWAS_EINVAL, "ctx is NULL");
-    if (form < 0 || form > 2) return fail(GWAS_EINVAL, "unknown form %d", form);
+    if (form < 0 || form > 3) return fail(GWAS_EINVAL, "unknown form %d", form);
     if (!(c->forms & GWAS_FORM_BIT(form))) return fail(GWAS_EINVAL, "form %d is not resident", form);
     if (i0 < 0 || mi < 0 || i0 + mi > c->m_cap)
         return fail(GWAS_EINVAL, "SNP range [%lld, %lld) outside capacity %lld", (long long)i0,
@@ -315,7 +320,7 @@ gwas_status prep_traits(gwas_ctx *c, int j0, int jb, const double *Y, int32_t y_
         ysrc = c->y_in;
     }
     HIP_TRY(hipMemcpyAsync(c->h2, h2 + j0, sizeof(double) * jb, hipMemcpyHostToDevice, s));
-    RotOut ro{c->yt, nullptr, nullptr, 0, 0, c->n_pad};
+    RotOut ro{c->yt, nullptr, nullptr, nullptr, 0, 0, c->n_pad};
     HIP_TRY(launch_rotate(ysrc, GWAS_DT_F64, jb, c->n, c->n, c->Z, c->n_pad, ro, s));
     PrepArgs pa{c->yt, c->h2, c->w, c->xlt, c->panels[form], c->fac, jb, c->n, c->n_pad, c->p, c->tcap,
                 fac_stride(c->p), form};
@@ -326,7 +331,8 @@ gwas_status prep_traits(gwas_ctx *c, int j0, int jb, const double *Y, int32_t y_
 FusedArgs fused_args(gwas_ctx *c, int jb, int32_t form, int tb_call) {
     FusedArgs fa{};
     fa.a = form == GWAS_FORM_F64 ? (const void *)c->xr64
-         : form == GWAS_FORM_F32 ? (const void *)c->xr32 : (const void *)c->xrbf;
+         : form == GWAS_FORM_F32 ? (const void *)c->xr32
+         : form == GWAS_FORM_BF16X3 ? (const void *)c->xrbf : (const void *)c->xrbf3;
     fa.a_plane_rows = c->m_rows;
     fa.panels = c->panels[form];
     fa.tcap = c->tcap;
@@ -624,7 +630,7 @@ gwas_status gwas_solve_snp_stream(gwas_ctx *c, const void *X_R, int32_t dtype, i
         HIP_TRY(hipMemcpyAsync(c->xin[h], (const uint8_t *)X_R + (size_t)g0 * c->n * esz,
                                (size_t)cnt * c->n * esz, hipMemcpyDefault, c->aux));
         c->bytes_h2d += (int64_t)cnt * c->n * (int64_t)esz;
-        RotOut ro{c->xr64, c->xr32, c->xrbf, c->m_rows, (int64_t)h * B, c->n_pad};
+        RotOut ro{c->xr64, c->xr32, c->xrbf, c->xrbf3, c->m_rows, (int64_t)h * B, c->n_pad};
         HIP_TRY(timed_begin(c, c->aux, ev));
         HIP_TRY(launch_rotate(c->xin[h], dtype, cnt, c->n, c->n, c->Z, c->n_pad, ro, c->aux));
         HIP_TRY(timed_end(c, c->aux, ev, c->t_rot));
@@ -730,8 +736,8 @@ int64_t gwas_debug_size(gwas_ctx *c, int32_t what, int32_t form) {
     case GWAS_DBG_YT: return (int64_t)sizeof(double) * c->tcap * np;
     case GWAS_DBG_FAC: return (int64_t)sizeof(double) * c->tcap * fac_stride(c->p);
     case GWAS_DBG_PANELS:
-        if (form < 0 || form > 2 || !(c->forms & GWAS_FORM_BIT(form))) return -1;
-        return (int64_t)elt_size(form) * (form == GWAS_FORM_BF16X3 ? 2 : 1) * (c->p + 1) * c->tcap * np;
+        if (form < 0 || form > 3 || !(c->forms & GWAS_FORM_BIT(form))) return -1;
+        return (int64_t)elt_size(form) * panel_planes(form) * (c->p + 1) * c->tcap * np;
     default: return -1;
     }
 }

@@ -92,11 +92,12 @@ struct gwas_ctx {
     double *xr64 = nullptr;  // [m_rows][n_pad]
     float *xr32 = nullptr;   // [m_rows][n_pad]
     uint16_t *xrbf = nullptr;  // 2 planes (x' hi, lo) [m_rows][n_pad]
+    uint16_t *xrbf3 = nullptr; // 3 planes (x' hi, mid, lo) [m_rows][n_pad]
 
     double *y_in = nullptr;  // [tcap][n] staging of host traits
     double *yt = nullptr;    // [tcap][n_pad]
     double *h2 = nullptr;    // [tcap]
-    void *panels[3] = {nullptr, nullptr, nullptr};  // per form
+    void *panels[4] = {nullptr, nullptr, nullptr, nullptr};  // per form
     double *fac = nullptr;   // [tcap][fac_stride]
     unsigned long long *counters = nullptr;  // [0] non-SPD problems; [4..7] persistent tile counters
 

@@ -18,6 +18,8 @@
 //   F32:    float operands,  v_mfma_f32_16x16x4f32 (optional FP64 folding)
 //   BF16X3: bf16 hi/lo operands, v_mfma_f32_16x16x32_bf16, three products
 //           hi*hi + hi*lo + lo*hi per pair, FP32 accumulation
+//   BF16X6: bf16 hi/mid/lo operands, six products (all but mid*lo, lo*mid,
+//           lo*lo), FP32 accumulation added to FP64 sums every 32 samples
 //
 // The tile kernels (operand staging, MFMA loops) are in fused_dma.h; this
 // header holds what every form shares: the split-BF16 square and the FP64
@@ -90,6 +92,23 @@ __device__ __forceinline__ bool gls_solve_store(const FusedArgs &a, const double
         for (int v = 0; v < P; ++v) bo[v] = ok ? (float)out[v] : __builtin_nanf("");
     }
     return ok;
+}
+
+// Three-piece square: the hi/mid/lo split of x'^2 from x' = hi + mid + lo
+// (exact in FP32), its square rounded to FP32 and split in three.
+__device__ __forceinline__ void square_split3(const bf16x8 &h, const bf16x8 &m, const bf16x8 &l, bf16x8 &sh,
+                                              bf16x8 &sm, bf16x8 &sl) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const float x = (float)h[e] + (float)m[e] + (float)l[e];
+        const float s = x * x;
+        const __bf16 s_hi = (__bf16)s;
+        const float r = s - (float)s_hi;
+        const __bf16 s_md = (__bf16)r;
+        sh[e] = s_hi;
+        sm[e] = s_md;
+        sl[e] = (__bf16)(r - (float)s_md);
+    }
 }
 
 // FP64 epilogue: Gram assembly and the p x p solve, lane-local. get(q, x, y,

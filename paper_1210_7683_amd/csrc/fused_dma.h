@@ -39,14 +39,16 @@ struct DmaTile {
 template <int FORM, int P, class T>
 struct DmaCfg {
     static constexpr int WM = T::WM, WN = T::WN, FM = T::FM, FN = T::FN, KB = T::KB;
-    static constexpr bool BF = FORM == GWAS_FORM_BF16X3;
+    static constexpr bool BF6 = FORM == GWAS_FORM_BF16X6;
+    static constexpr bool BF = FORM == GWAS_FORM_BF16X3 || BF6;
+    static constexpr int PIECES = FORM == GWAS_FORM_BF16X3 ? 2 : (BF6 ? 3 : 1);   // BF16 pieces per value
     static constexpr int NW = WM * WN;
     static constexpr int NT = 64 * NW;
     static constexpr int TM = WM * FM * 16, TN = WN * FN * 16;
     static constexpr int NQ = P + 1;
     static constexpr int ESZ = FORM == GWAS_FORM_F64 ? 8 : (FORM == GWAS_FORM_F32 ? 4 : 2);
-    static constexpr int NA = BF ? 2 : 1;               // staged SNP-side planes
-    static constexpr int NB = BF ? 2 * NQ : NQ;         // staged trait-side planes
+    static constexpr int NA = PIECES;                   // staged SNP-side planes
+    static constexpr int NB = PIECES * NQ;              // staged trait-side planes
     static constexpr int GA = NA * (TM / 16);           // blocks of one 64-byte group
     static constexpr int GBK = GA + NB * (TN / 16);
     static constexpr int BLK = KB * GBK;                // blocks per stage
@@ -59,7 +61,7 @@ struct DmaCfg {
     // fragments (plane, x) then the trait fragments (plane, y); offsets are
     // from the wave's SNP base (stage + lane * 16 + wm * FM KB) or trait base
     // (stage + lane * 16 + (GA + wn * FN) KB)
-    static constexpr int NBP = BF ? 2 * NQ : NQ;
+    static constexpr int NBP = NB;
     static constexpr int NFA = NA * FM, NFK = NFA + NBP * FN, NF = KB * NFK;
     static constexpr bool frag_is_b(int i) { return (i % NFK) >= NFA; }
     static constexpr int frag_off(int i) {
@@ -76,6 +78,7 @@ struct DmaFrag;
 template <> struct DmaFrag<GWAS_FORM_F64> { using type = double2; using acc = d4; };
 template <> struct DmaFrag<GWAS_FORM_F32> { using type = float4; using acc = f4; };
 template <> struct DmaFrag<GWAS_FORM_BF16X3> { using type = bf16x8; using acc = f4; };
+template <> struct DmaFrag<GWAS_FORM_BF16X6> { using type = bf16x8; using acc = f4; };
 
 // One TM x TN tile of problems (tile index over the tiles of a, traits fastest),
 // computed by a whole workgroup of C::NT threads with `lds` (C::LDS bytes,
@@ -89,7 +92,8 @@ __device__ __forceinline__ void dma_tile(const FusedArgs &a, int64_t tile, uint8
     using acc_t = typename DmaFrag<FORM>::acc;
     constexpr int NQ = C::NQ, TM = C::TM, TN = C::TN, FM = C::FM, FN = C::FN, KB = C::KB, NA = C::NA;
     constexpr bool BF = C::BF;
-    static_assert(!FLUSH || (FORM == GWAS_FORM_F32 && KB == 2), "the FP64 fold is per 32-sample FP32 window");
+    static_assert(!FLUSH || (FORM == GWAS_FORM_F32 && KB == 2) || (FORM == GWAS_FORM_BF16X6 && KB == 1),
+                  "the FP64 fold is per 32-sample stage");
 
     const int ntn = (a.tb + TN - 1) / TN;
     const int tn = (int)(tile % ntn);
@@ -247,6 +251,25 @@ __device__ __forceinline__ void dma_tile(const FusedArgs &a, int64_t tile, uint8
                             }
                         }
                     }
+                } else if constexpr (C::BF6) {
+                    // x = h + m + l; six products per pair, smallest first
+                    const bf16x8 xh = xa[kb][0][x], xm = xa[kb][1][x], xl = xa[kb][2][x];
+                    bf16x8 sh, sm, sl;
+                    square_split3(xh, xm, xl, sh, sm, sl);
+#pragma unroll
+                    for (int y = 0; y < FN; ++y)
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q) {
+                            const bf16x8 ah = q == 0 ? sh : xh, am = q == 0 ? sm : xm, al = q == 0 ? sl : xl;
+                            const bf16x8 bh = yb[kb][3 * q][y], bm = yb[kb][3 * q + 1][y], bl = yb[kb][3 * q + 2][y];
+                            f4 v = fresh ? f4{0, 0, 0, 0} : acc[q][x][y];
+                            v = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, v, 0, 0, 0);
+                            v = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, v, 0, 0, 0);
+                            v = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, v, 0, 0, 0);
+                            v = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, v, 0, 0, 0);
+                            v = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, v, 0, 0, 0);
+                            acc[q][x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, v, 0, 0, 0);
+                        }
                 } else {
                     const bf16x8 xh = xa[kb][0][x], xl = xa[kb][1][x];
                     bf16x8 sh, sl;
@@ -380,8 +403,15 @@ struct DmaDefault {
     using BF16T = typename std::conditional<(P <= 4), DmaTile<8, 1, 2, 2, 1, true, true>,
                   typename std::conditional<(P <= 9), DmaTile<8, 1, 2, 1, 1, true>,
                                             DmaTile<4, 1, 1, 1, 1, true>>::type>::type;
+    // six-product form: three planes a side; the two-stage pipeline's 16-bit
+    // fragment offsets bound the stage to 64 blocks
+    using BF6T = typename std::conditional<(P <= 4), DmaTile<8, 1, 1, 2, 1, true>,
+                 typename std::conditional<(P <= 9), DmaTile<8, 1, 1, 1, 1, true>,
+                 typename std::conditional<(P <= 16), DmaTile<4, 1, 1, 1, 1, true>,
+                                           DmaTile<4, 1, 1, 1, 1>>::type>::type>::type;
     using type = typename std::conditional<FORM == GWAS_FORM_F64, F64T,
-                 typename std::conditional<FORM == GWAS_FORM_F32, F32T, BF16T>::type>::type;
+                 typename std::conditional<FORM == GWAS_FORM_F32, F32T,
+                 typename std::conditional<FORM == GWAS_FORM_BF16X3, BF16T, BF6T>::type>::type>::type;
 };
 
 template <int FORM, bool FLUSH>

@@ -17,7 +17,7 @@ constexpr int kPadN = 64;
 // whose S_BR - |L^{-1} S_BL|^2 does not exceed this fraction of S_BR is
 // treated as rank-deficient (b = NaN). It scales with the contraction
 // precision: the pivot's computed value is noise below it.
-constexpr double kRankRtol[3] = {1e-10, 1e-4, 1e-3};
+constexpr double kRankRtol[4] = {1e-10, 1e-4, 1e-3, 1e-4};
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -71,11 +71,21 @@ __device__ __forceinline__ void bf16_split(float x, uint16_t &hi, uint16_t &lo) 
     lo = bf16_rne(x - bf16_to_f32(hi));
 }
 
+// x = hi + mid + lo exactly (24 bits in three BF16 pieces); each residual is
+// exact in FP32.
+__device__ __forceinline__ void bf16_split3(float x, uint16_t &hi, uint16_t &mid, uint16_t &lo) {
+    hi = bf16_rne(x);
+    const float r = x - bf16_to_f32(hi);
+    mid = bf16_rne(r);
+    lo = bf16_rne(r - bf16_to_f32(mid));
+}
+
 // Output planes of a rotation (any pointer may be null).
 struct RotOut {
     double *f64;      // [rows][ld]
     float *f32;       // [rows][ld]
     uint16_t *bf;     // 2 planes, each [plane_rows][ld]: x hi, x lo
+    uint16_t *bf3;    // 3 planes, each [plane_rows][ld]: x hi, mid, lo
     int64_t plane_rows;
     int64_t row0;     // first output row
     int ld;           // n_pad
@@ -128,13 +138,13 @@ hipError_t launch_fused(int form, const FusedArgs &a, hipStream_t s);
 // fit the dot-product kernel's LDS copy, use that kernel (HBM-bound,
 // fused_gemv.h) instead of the MFMA tiles; measured on MI355X at n = 1000,
 // p = 4, it is faster there (the split-BF16 MFMA tiles are not slower at any
-// t). The choice is per call, so every problem of a call is computed the same
+// t, and both split-BF16 forms keep them). The choice is per call, so every problem of a call is computed the same
 // way whatever the sub-blocking.
 constexpr int kSmallT = 3;
 constexpr int64_t kGemvLdsMax = 64 * 1024;
 inline bool use_dot_kernel(int form, int p, int tb_call, int n_pad) {
     const int64_t lds = (int64_t)(p + 1) * tb_call * n_pad * (form == GWAS_FORM_F64 ? 8 : 4);
-    return form != GWAS_FORM_BF16X3 && tb_call <= kSmallT && lds <= kGemvLdsMax;
+    return (form == GWAS_FORM_F64 || form == GWAS_FORM_F32) && tb_call <= kSmallT && lds <= kGemvLdsMax;
 }
 
 // Copy `bytes` (a multiple of 4; 16-byte aligned pointers) from device memory
@@ -143,5 +153,6 @@ hipError_t launch_copy_to_host(void *dst_dev_view, const void *src, int64_t byte
 hipError_t launch_fused_f64(const FusedArgs &a, hipStream_t s);
 hipError_t launch_fused_f32(const FusedArgs &a, hipStream_t s);
 hipError_t launch_fused_bf16(const FusedArgs &a, hipStream_t s);
+hipError_t launch_fused_bf16x6(const FusedArgs &a, hipStream_t s);
 
 }  // namespace gw

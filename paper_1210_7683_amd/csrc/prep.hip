@@ -37,12 +37,20 @@ __device__ __forceinline__ void put(void *panels, int plane, int tcap, int j, in
         ((double *)panels)[o] = v;
     } else if constexpr (FORM == GWAS_FORM_F32) {
         ((float *)panels)[o] = (float)v;
-    } else {
+    } else if constexpr (FORM == GWAS_FORM_BF16X3) {
         uint16_t h, l;
         bf16_split((float)v, h, l);
         const int64_t o2 = ((int64_t)(2 * plane) * tcap + j) * n_pad + k;
         ((uint16_t *)panels)[o2] = h;
         ((uint16_t *)panels)[o2 + (int64_t)tcap * n_pad] = l;
+    } else {
+        uint16_t h, md, l;
+        bf16_split3((float)v, h, md, l);
+        const int64_t o3 = ((int64_t)(3 * plane) * tcap + j) * n_pad + k;
+        const int64_t ps = (int64_t)tcap * n_pad;
+        ((uint16_t *)panels)[o3] = h;
+        ((uint16_t *)panels)[o3 + ps] = md;
+        ((uint16_t *)panels)[o3 + 2 * ps] = l;
     }
 }
 
@@ -135,6 +143,7 @@ hipError_t launch_prep(const PrepArgs &a, hipStream_t s) {
     case GWAS_FORM_F64: hipLaunchKernelGGL(prep_kernel<GWAS_FORM_F64>, grid, block, 0, s, a); break;
     case GWAS_FORM_F32: hipLaunchKernelGGL(prep_kernel<GWAS_FORM_F32>, grid, block, 0, s, a); break;
     case GWAS_FORM_BF16X3: hipLaunchKernelGGL(prep_kernel<GWAS_FORM_BF16X3>, grid, block, 0, s, a); break;
+    case GWAS_FORM_BF16X6: hipLaunchKernelGGL(prep_kernel<GWAS_FORM_BF16X6>, grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -5,8 +5,8 @@
 // (v_mfma_f64_16x16x4f64) over LDS-staged K chunks.
 //
 // The rotated rows are written in every resident form at once: FP64, rounded
-// to FP32, and split to BF16 hi/lo (the split of x'^2 is formed by the fused
-// kernels from hi/lo).
+// to FP32, split to BF16 hi/lo, and split to BF16 hi/mid/lo (the splits of
+// x'^2 are formed by the fused kernels from these).
 #include "gwas_internal.h"
 #include "lds_dma.h"
 
@@ -39,6 +39,14 @@ __device__ __forceinline__ void rot_store(const RotOut &out, int64_t i, int k, d
         bf16_split((float)v, h, l);
         out.bf[o] = h;
         out.bf[out.plane_rows * out.ld + o] = l;
+    }
+    if (out.bf3) {
+        uint16_t h, md, l;
+        bf16_split3((float)v, h, md, l);
+        const int64_t ps = out.plane_rows * out.ld;
+        out.bf3[o] = h;
+        out.bf3[ps + o] = md;
+        out.bf3[2 * ps + o] = l;
     }
 }   // fastest of a tile sweep on MI355X (n = 1000)
 

@@ -241,7 +241,7 @@ gwas_status start_request(gwas_server *s, Req *r) {
     HIP_TRY(hipMemcpyAsync(r->d_y, s->slot_y[r->slot], sizeof(double) * r->y.size(), hipMemcpyHostToDevice,
                            s->s_comp));
     HIP_TRY(hipMemcpyAsync(r->d_h2, s->slot_h2[r->slot], sizeof(double) * r->t, hipMemcpyHostToDevice, s->s_comp));
-    RotOut ro{r->d_yt, nullptr, nullptr, 0, 0, c->n_pad};
+    RotOut ro{r->d_yt, nullptr, nullptr, nullptr, 0, 0, c->n_pad};
     HIP_TRY(launch_rotate(r->d_y, GWAS_DT_F64, r->t, c->n, c->n, c->Z, c->n_pad, ro, s->s_comp));
     PrepArgs pa{r->d_yt, r->d_h2, c->w, c->xlt, r->d_panels, r->d_fac, r->t, c->n, c->n_pad, r->p, r->t,
                 fac_stride(r->p), s->form};
@@ -547,6 +547,8 @@ gwas_status gwas_server_create(gwas_ctx *c, const gwas_server_options *opt, gwas
     if (!out) return fail(GWAS_EINVAL, "server pointer is NULL");
     *out = nullptr;
     if (!c || !opt) return fail(GWAS_EINVAL, "NULL argument");
+    if (opt->form == GWAS_FORM_BF16X6)
+        return fail(GWAS_EINVAL, "form %d is not served (FP64, FP32 and three-product split BF16 are)", opt->form);
     if (opt->form < 0 || opt->form > 2 || !(c->forms & GWAS_FORM_BIT(opt->form)))
         return fail(GWAS_EINVAL, "form %d is not resident", opt->form);
     if (opt->hbm_budget < 0 || opt->max_slots < 0 || opt->max_slots > kServeMaxItems || opt->item_problems < 0 ||

@@ -16,8 +16,8 @@ LIB_PATH = os.path.join(_HERE, "libgwas.so")
 
 OK, EINVAL, ENOMEM, EHIP, EBUSY, ESTATE = 0, 1, 2, 3, 4, 5
 DT_F64, DT_F32, DT_U8 = 0, 1, 2
-FORM_F64, FORM_F32, FORM_BF16X3 = 0, 1, 2
-FORMS = {"f64": FORM_F64, "f32": FORM_F32, "bf16x3": FORM_BF16X3}
+FORM_F64, FORM_F32, FORM_BF16X3, FORM_BF16X6 = 0, 1, 2, 3
+FORMS = {"f64": FORM_F64, "f32": FORM_F32, "bf16x3": FORM_BF16X3, "bf16x6": FORM_BF16X6}
 
 _lib = None
 
@@ -384,7 +384,7 @@ class Cohort:
         size = load().gwas_debug_size(self._h, code, f)
         if size < 0:
             raise ValueError("no such buffer")
-        dt = np.uint16 if (what == "panels" and f == FORM_BF16X3) else \
+        dt = np.uint16 if (what == "panels" and f in (FORM_BF16X3, FORM_BF16X6)) else \
             (np.float32 if (what == "panels" and f == FORM_F32) else np.float64)
         out = np.empty(size // np.dtype(dt).itemsize, dtype=dt)
         _check(load().gwas_debug_copy(self._h, code, f, out.ctypes.data, size))

@@ -5,8 +5,11 @@ import oracle
 from paper_1210_7683_amd import gwas
 
 # Error bounds of b against the FP64 oracle, per form: FP64 and FP32 are the
-# stated targets; split BF16 is the measured bound, with margin.
-TOL = {"f64": 1e-10, "f32": 1e-5, "bf16x3": 2e-4}
+# stated targets; the three-piece split BF16 form carries the FP32 value exactly
+# and drops products below FP32 rounding, so it takes the FP32 target; the
+# two-piece form's bound is the measured one, with margin.
+TOL = {"f64": 1e-10, "f32": 1e-5, "bf16x3": 2e-4, "bf16x6": 1e-5}
+ALL_FORMS = ("f64", "f32", "bf16x3", "bf16x6")
 
 
 def rel_err(b_hat, b_ref):
@@ -29,7 +32,7 @@ def scaled_err(b_hat, b_ref, trait_axis=1):
     return np.linalg.norm(b_hat - b_ref, axis=-1) / np.maximum(nb, med)
 
 
-def cohort(phi, xl, xr, forms=("f64", "f32", "bf16x3"), m_capacity=None, **kw):
+def cohort(phi, xl, xr, forms=ALL_FORMS, m_capacity=None, **kw):
     w, z = np.linalg.eigh(phi)
     c = gwas.Cohort(z, w, xl, m_capacity or xr.shape[0], forms=forms, **kw)
     c.rotate(0, xr)

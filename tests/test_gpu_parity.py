@@ -15,11 +15,11 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_common import TOL, cohort, rel_err, scaled_err
+from tests.gpu_common import ALL_FORMS, TOL, cohort, rel_err, scaled_err
 
 pytestmark = pytest.mark.gpu
 
-FORMS = ["f64", "f32", "bf16x3"]
+FORMS = list(ALL_FORMS)
 
 
 @pytest.fixture(scope="module")
@@ -131,7 +131,7 @@ def test_small_trait_calls_use_the_dot_product_kernel(form, n, p, m, t, torch_cu
     c = cohort(phi, xl, xr, forms=(form,), slab_snps=32)
     b = c.solve(y, h2, form=form).cpu().numpy()
     n_pad = (n + 63) // 64 * 64
-    dot = form != "bf16x3" and t <= 3 and (p + 1) * t * n_pad * (8 if form == "f64" else 4) <= 64 * 1024
+    dot = form in ("f64", "f32") and t <= 3 and (p + 1) * t * n_pad * (8 if form == "f64" else 4) <= 64 * 1024
     assert c.stats()["dot_launches"] == (1 if dot else 0)
     err, sc = rel_err(b, ref), scaled_err(b, ref)
     print("n=%d p=%d m=%d t=%d %s: relative max %.3e, scaled max %.3e" % (n, p, m, t, form,
@@ -240,7 +240,7 @@ def paper_m1e5(torch_cuda):
     y, h2 = synth.traits(w)
     ev, z = np.linalg.eigh(phi)
     from paper_1210_7683_amd import gwas
-    c = gwas.Cohort(z, ev, xl, w.m)
+    c = gwas.Cohort(z, ev, xl, w.m, forms=ALL_FORMS)
     c.rotate(0, torch.from_numpy(xr).cuda())
     yd = torch.from_numpy(y).cuda()
     yield dict(w=w, phi=phi, xl=xl, y=y, h2=h2, c=c, yd=yd)
@@ -309,7 +309,7 @@ def test_large_n_sampled_against_oracle(torch_cuda):
     ref = oracle.gls(phi, xl, xr[ii], y, h2, trait=jj)
     w, z = np.linalg.eigh(phi)
     from paper_1210_7683_amd import gwas
-    with gwas.Cohort(z, w, xl, m) as c:
+    with gwas.Cohort(z, w, xl, m, forms=ALL_FORMS) as c:
         c.rotate(0, torch.from_numpy(xr).cuda())
         for form in FORMS:
             b = c.solve(y, h2, form=form)

@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_common import TOL, rel_err, scaled_err
+from tests.gpu_common import ALL_FORMS, TOL, rel_err, scaled_err
 
 pytestmark = pytest.mark.gpu
 
@@ -39,10 +39,10 @@ def test_precision_study_paper_m1e6():
     print("oracle: %d problems over %d traits in %.1f s" % (ii.size, uj.size, time.perf_counter() - t0),
           flush=True)
     ti, tj = torch.from_numpy(ii).cuda(), torch.from_numpy(jj).cuda()
-    with gwas.Cohort(z, ev, xl, w.m) as c:
+    with gwas.Cohort(z, ev, xl, w.m, forms=ALL_FORMS) as c:
         c.rotate(0, torch.from_numpy(xr).cuda())
         yd = torch.from_numpy(y).cuda()
-        for form in ("f64", "f32", "bf16x3"):
+        for form in ALL_FORMS:
             b = c.solve(yd, h2, form=form)
             got = b[ti, tj].cpu().numpy()
             finite = bool(torch.isfinite(b).all())

@@ -129,6 +129,8 @@ def test_cancel_and_errors(cohort_f32):
             srv.poll(12345)
     with pytest.raises(gwas.GwasError):
         gwas.Server(d["c"], form="f64", item_problems=2000, max_traits=64)   # form not resident
+    with pytest.raises(gwas.GwasError, match="not served"):
+        gwas.Server(d["c"], form="bf16x6", item_problems=2000, max_traits=64)
     with gwas.Server(d["c"], form="f32", hbm_budget=1 << 16, item_problems=2000, max_traits=64) as small:
         with pytest.raises(gwas.GwasError):       # can never fit the budget
             small.submit(y, h2, 4)

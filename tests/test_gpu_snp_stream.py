@@ -7,11 +7,11 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_common import TOL, cohort, scaled_err
+from tests.gpu_common import ALL_FORMS, TOL, cohort, scaled_err
 
 pytestmark = pytest.mark.gpu
 
-FORMS = ["f64", "f32", "bf16x3"]
+FORMS = list(ALL_FORMS)
 
 
 @pytest.fixture(scope="module")
