@@ -351,7 +351,7 @@ def main():
     ap.add_argument("--skip-checksum", action="store_true", help="serving: do not checksum ring slabs")
     ap.add_argument("--grid-wgs", type=int, default=0, help="serving: persistent workgroups (0: two per CU)")
     ap.add_argument("--profile-pass", action="store_true",
-                    help="one step of the headline form plus a plain 1 GiB device copy (for counter "
+                    help="one step of each form in --forms plus a plain 1 GiB device copy (for counter "
                          "calibration), no timing output; meant to run under rocprofv3")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -398,18 +398,20 @@ def main():
     problems = w.m * w.t
     flops_gls = cm.flops_per_gls_contraction(w.n, w.p)
     if args.profile_pass:
-        form = forms[0]
-        with gwas.Cohort(z, ev, xl, w.m, forms=(form,), f32_flush=args.f32_flush) as cohort:
-            b = torch.empty((w.m, w.t, w.p), dtype=torch.float64 if form == "f64" else torch.float32,
-                            device="cuda")
-            cohort.rotate(0, xr_d)
-            cohort.solve(y_d, h2, form=form, out=b)
-            torch.cuda.synchronize()
+        for form in forms:
+            with gwas.Cohort(z, ev, xl, w.m, forms=(form,), f32_flush=args.f32_flush) as cohort:
+                b = torch.empty((w.m, w.t, w.p), dtype=torch.float64 if form == "f64" else torch.float32,
+                                device="cuda")
+                cohort.rotate(0, xr_d)
+                cohort.solve(y_d, h2, form=form, out=b)
+                torch.cuda.synchronize()
+                del b
+            log("profile pass: one %s step" % form)
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        log("profile pass done: one %s step and a 1 GiB device copy" % form)
+        log("profile pass done: a 1 GiB device copy")
         return
     results = {}
     for form in forms:

@@ -80,7 +80,7 @@ void release(gwas_ctx *c) {
         }
     void *ptrs[] = {c->Z, c->w, c->xlt, c->xr64, c->xr32, c->xrbf, c->y_in, c->yt, c->h2,
                     c->panels[0], c->panels[1], c->panels[2], c->panels[3], c->xrbf3, c->fac, c->counters, c->stage,
-                    c->bstage[0], c->bstage[1], c->xin[0], c->xin[1]};
+                    c->bstage[0], c->bstage[1], c->xin[0], c->xin[1], c->zq, c->zoff, c->zscale};
     for (void *p : ptrs)
         if (p) hipFree(p);
     for (int i = 0; i < 2; ++i) {
@@ -183,6 +183,11 @@ gwas_status gwas_setup(gwas_ctx **out, int32_t n, int32_t p, const double *Z, co
     const int np = c->n_pad;
 #define TRY(x) do { if ((st = (x)) != GWAS_OK) { release(c); return st; } } while (0)
     TRY(dalloc(c, &c->Z, sizeof(double) * np * np));
+    if (np <= kZSliceMaxNpad) {
+        TRY(dalloc(c, &c->zq, (size_t)kZSlices * np * np));
+        TRY(dalloc(c, &c->zoff, sizeof(double) * np));
+        TRY(dalloc(c, &c->zscale, sizeof(double) * np));
+    }
     TRY(dalloc(c, &c->w, sizeof(double) * np));
     TRY(dalloc(c, &c->xlt, sizeof(double) * (size_t)(p - 1) * np));
     const size_t plane = (size_t)c->m_rows * np;
@@ -210,6 +215,14 @@ gwas_status gwas_setup(gwas_ctx **out, int32_t n, int32_t p, const double *Z, co
         if (!zh) { release(c); return fail(GWAS_ENOMEM, "host allocation"); }
         for (int k = 0; k < n; ++k) memcpy(zh + (size_t)k * np, Z + (size_t)k * n, sizeof(double) * n);
         hipError_t e = hipMemcpy(c->Z, zh, sizeof(double) * np * np, hipMemcpyHostToDevice);
+        if (e == hipSuccess && c->zq) {   // int8 digits of Z for the genotype rotation
+            std::vector<int8_t> q((size_t)kZSlices * np * np);
+            std::vector<double> off(np), sc(np);
+            slice_z_int8(zh, np, q.data(), off.data(), sc.data());
+            e = hipMemcpy(c->zq, q.data(), q.size(), hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipMemcpy(c->zoff, off.data(), sizeof(double) * np, hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipMemcpy(c->zscale, sc.data(), sizeof(double) * np, hipMemcpyHostToDevice);
+        }
         free(zh);
         if (e != hipSuccess) { release(c); return fail(GWAS_EHIP, "upload Z: %s", hipGetErrorString(e)); }
         double *wh = (double *)malloc(sizeof(double) * np);
@@ -261,11 +274,12 @@ gwas_status gwas_rotate(gwas_ctx *c, int64_t m0, int64_t mb, const void *X, int3
     hipStream_t s = (hipStream_t)stream;
     const size_t esz = dtype == GWAS_DT_F64 ? 8 : (dtype == GWAS_DT_F32 ? 4 : 1);
     RotOut ro{c->xr64, c->xr32, c->xrbf, c->xrbf3, c->m_rows, 0, c->n_pad};
+    const ZSlices zs = c->zs();
     std::pair<hipEvent_t, hipEvent_t> ev{};
     if (on_device) {
         ro.row0 = m0;
         HIP_TRY(timed_begin(c, s, ev));
-        HIP_TRY(launch_rotate(X, dtype, mb, c->n, c->n, c->Z, c->n_pad, ro, s));
+        HIP_TRY(launch_rotate(X, dtype, mb, c->n, c->n, c->Z, c->n_pad, ro, s, &zs));
         HIP_TRY(timed_end(c, s, ev, c->t_rot));
     } else {
         const int64_t per = std::max<int64_t>(1, (int64_t)(c->stage_bytes / (esz * c->n)));
@@ -276,7 +290,7 @@ gwas_status gwas_rotate(gwas_ctx *c, int64_t m0, int64_t mb, const void *X, int3
                                    hipMemcpyHostToDevice, s));
             ro.row0 = m0 + done;
             HIP_TRY(timed_begin(c, s, ev));
-            HIP_TRY(launch_rotate(c->stage, dtype, cnt, c->n, c->n, c->Z, c->n_pad, ro, s));
+            HIP_TRY(launch_rotate(c->stage, dtype, cnt, c->n, c->n, c->Z, c->n_pad, ro, s, &zs));
             HIP_TRY(timed_end(c, s, ev, c->t_rot));
             c->bytes_h2d += (int64_t)bytes;
         }
@@ -632,7 +646,8 @@ gwas_status gwas_solve_snp_stream(gwas_ctx *c, const void *X_R, int32_t dtype, i
         c->bytes_h2d += (int64_t)cnt * c->n * (int64_t)esz;
         RotOut ro{c->xr64, c->xr32, c->xrbf, c->xrbf3, c->m_rows, (int64_t)h * B, c->n_pad};
         HIP_TRY(timed_begin(c, c->aux, ev));
-        HIP_TRY(launch_rotate(c->xin[h], dtype, cnt, c->n, c->n, c->Z, c->n_pad, ro, c->aux));
+        const ZSlices zs = c->zs();
+        HIP_TRY(launch_rotate(c->xin[h], dtype, cnt, c->n, c->n, c->Z, c->n_pad, ro, c->aux, &zs));
         HIP_TRY(timed_end(c, c->aux, ev, c->t_rot));
         HIP_TRY(hipEventRecord(c->ev_rot[h], c->aux));
         c->snps_rotated += cnt;

@@ -87,6 +87,8 @@ struct gwas_ctx {
     double w_min = 0.0;
 
     double *Z = nullptr;     // [n_pad][n_pad]: row k = eigenvector k (zeros beyond n)
+    int8_t *zq = nullptr;    // int8 digits of Z for the genotype rotation (ZSlices)
+    double *zoff = nullptr, *zscale = nullptr;   // [n_pad] each
     double *w = nullptr;     // [n_pad]
     double *xlt = nullptr;   // [p-1][n_pad]
     double *xr64 = nullptr;  // [m_rows][n_pad]
@@ -124,6 +126,8 @@ struct gwas_ctx {
     std::vector<void *> ring_dev;   // device-side addresses of the ring slots
     size_t ring_bytes = 0;
     std::vector<hipEvent_t> ring_ev;
+
+    gw::ZSlices zs() const { return gw::ZSlices{zq, zoff, zscale}; }
 
     int64_t snps_rotated = 0, problems = 0, bytes_h2d = 0, bytes_d2h = 0, resident = 0, dot_launches = 0;
 

@@ -91,9 +91,31 @@ struct RotOut {
     int ld;           // n_pad
 };
 
-// out[row0 + i][k] = sum_r X[i][r] Z[k][r]  for i < rows, k < n_pad (FP64 MFMA).
+// Z in fixed point, sliced into int8 digits, for the genotype rotation on the
+// int8 MFMAs: row k of Z is scaled by 2^E_k and rounded to an integer q_k[r]
+// with |q_k| <= 2^(8 kZSlices - 2); q_k = sum_d 256^(kZSlices-1-d) s_d with
+// balanced digits s_d in [-128, 127]. For genotype bytes v (offset to
+// a = v - 128, exact in int8) every digit's contraction sum_r a_r s_d[k][r] is
+// exact in int32 (|.| <= 2^14 n_pad), and
+//   x'[k] = 2^-E_k (sum_d 256^(kZSlices-1-d) acc_d + 128 sum_r q_k[r]).
+// The only error is the rounding of Z to 8 kZSlices - 1 bits (relative to the
+// row's largest entry): with 6 digits below 1e-14 of x' for unit-norm rows.
+constexpr int kZSlices = 6;
+constexpr int kZSliceMaxNpad = 1 << 17;   // int32 headroom of the digit sums
+struct ZSlices {
+    const int8_t *q;       // [kZSlices][n_pad][n_pad]: digit d of row k at (d n_pad + k) n_pad
+    const double *off;     // [n_pad]: 128 sum_r q_k[r]
+    const double *scale;   // [n_pad]: 2^-E_k (0 for an all-zero row)
+};
+// Host: slices of the padded row-major Z (row k = eigenvector k, zeros past n).
+void slice_z_int8(const double *zh, int n_pad, int8_t *q, double *off, double *scale);
+
+// out[row0 + i][k] = sum_r X[i][r] Z[k][r]  for i < rows, k < n_pad. Genotype
+// bytes (GWAS_DT_U8) with zs given and n_pad <= kZSliceMaxNpad use the int8
+// digit kernel; every other case FP64 MFMA.
 hipError_t launch_rotate(const void *X, int dtype, int64_t rows, int n, int64_t ldx,
-                         const double *Zrows, int n_pad, const RotOut &out, hipStream_t s);
+                         const double *Zrows, int n_pad, const RotOut &out, hipStream_t s,
+                         const ZSlices *zs = nullptr);
 
 // Per-trait prologue (FP64): weights, contraction panels, and the factor of S_TL.
 struct PrepArgs {

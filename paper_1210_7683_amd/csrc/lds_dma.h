@@ -22,6 +22,16 @@ __device__ __forceinline__ void lds_dma16(const uint8_t *g, uint8_t *l) {
                                      (void __attribute__((address_space(3))) *)l, 16, 0, 0);
 }
 
+// 4 bytes per lane: lane l's dword lands at LDS (wave-uniform base + 4 l).
+__device__ __forceinline__ void lds_dma4(const uint8_t *g, uint8_t *l) {
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)g,
+                                     (void __attribute__((address_space(3))) *)l, 4, 0, 0);
+}
+
+// s_waitcnt immediate that waits until at most n (< 64) vector memory
+// operations of this wave are outstanding (lgkmcnt and expcnt not waited).
+constexpr int vmcnt_imm(int n) { return 0x0F70 | (n & 15) | ((n >> 4) << 14); }
+
 typedef int i4v __attribute__((ext_vector_type(4)));
 
 // LDS byte address (offset within the workgroup's LDS) of a shared-memory pointer.

@@ -1,12 +1,20 @@
 // Rotation by Z^T (the preloop GEMMs of Algorithm 5, bundled over columns as
 // Section 3.2 describes): every input column x (n samples) becomes x' = Z^T x.
 // As a GEMM, out[i][k] = sum_r X[i][r] Z[k][r] (rows of Z are eigenvectors):
-// both operands are contiguous along the samples r, computed in FP64 MFMA
-// (v_mfma_f64_16x16x4f64) over LDS-staged K chunks.
+// both operands are contiguous along the samples r. FP64 and FP32 inputs are
+// computed in FP64 MFMA (v_mfma_f64_16x16x4f64) over LDS-staged K chunks;
+// genotype bytes on the int8 MFMAs against Z sliced into int8 digits, whose
+// sums are exact integers (the slicing of a floating-point operand into
+// integer digits with exact integer products and sums follows Ozaki's scheme
+// for emulating high-precision GEMM on integer matrix units).
 //
 // The rotated rows are written in every resident form at once: FP64, rounded
 // to FP32, split to BF16 hi/lo, and split to BF16 hi/mid/lo (the splits of
 // x'^2 are formed by the fused kernels from these).
+#include <math.h>
+
+#include <algorithm>
+
 #include "gwas_internal.h"
 #include "lds_dma.h"
 
@@ -301,7 +309,338 @@ __global__ __launch_bounds__(R::NT) void rotate_u8_dma_kernel(const uint8_t *__r
             }
 }
 
+// Genotype rotation on the int8 MFMAs (v_mfma_i32_16x16x64_i8) with Z sliced
+// into int8 digits (ZSlices). A stage covers KS k-steps of 64 samples. In
+// k-step ks, lane group g of a wave holds samples 16 g .. 16 g + 15 of each of
+// its SNP rows (16 genotype bytes straight from global memory, prefetched a
+// stage ahead, offset by -128 to signed bytes), and Z block (ks, d, cb) in LDS
+// holds for lane l the same 16 samples of digit d of row k0 + 16 cb + l % 16,
+// so both operands put sample s in the same MFMA slot. One MFMA per (digit,
+// SNP block, Z block) and k-step; the digit sums are exact int32, recombined
+// in FP64 by the epilogue. The next stage's Z blocks and genotypes load under
+// the MFMAs; k-steps at or past n_pad (the tail of the last stage) are skipped.
+template <int WM_, int WN_, int FM_, int FN_, int KS_ = 1>
+struct RotI8 {
+    static constexpr int WM = WM_, WN = WN_, FM = FM_, FN = FN_, KS = KS_, ND = kZSlices;
+    static constexpr int NW = WM * WN, NT = 64 * NW;
+    static constexpr int TM = WM * FM * 16, TN = WN * FN * 16;
+    static constexpr int CB = TN / 16;                  // 16-row Z blocks of the tile
+    static constexpr int ZK = ND * CB;                  // Z blocks of one k-step, digit-major
+    static constexpr int ZB = KS * ZK;                  // Z blocks per stage
+    static constexpr int LDS = 2 * ZB * 1024;
+    static constexpr int LPW = (ZB + NW - 1) / NW;      // Z block loads per wave and stage
+    static constexpr int NF = ND * FN;                  // fragments a wave reads per k-step, (digit, y)
+    static constexpr bool frag_is_b(int) { return false; }
+    static constexpr int frag_off(int i) { return ((i / FN) * CB + i % FN) * 1024; }   // from the wave's first block
+    static_assert(ZK * 1024 <= 65536 && LDS <= 160 * 1024, "rotation stage too large");
+};
+
+using DefaultRotI8 = RotI8<4, 2, 2, 1>;
+
+template <class R>
+__global__ __launch_bounds__(R::NT) void rotate_u8_i8_kernel(const uint8_t *__restrict__ X, int64_t rows, int n,
+                                                             int64_t ldx, ZSlices zs, int n_pad, RotOut out) {
+    constexpr int TN = R::TN, FM = R::FM, FN = R::FN, ND = R::ND, CB = R::CB, KS = R::KS;
+    extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
+    const int ntn = n_pad / TN;
+    const int64_t tile = tile_order(blockIdx.x, (rows + R::TM - 1) / R::TM, ntn);
+    const int tn = (int)(tile % ntn);
+    const int64_t tm = tile / ntn;
+    const int64_t i_base = tm * R::TM;
+    const int k_base = tn * TN;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave % R::WM, wn = wave / R::WM;
+    const int l16 = lane & 15, g = lane >> 4;
+    const int nk = (n + 63) / 64;                 // k-steps; 64 nk <= n_pad
+    const int nst = (nk + KS - 1) / KS;           // stages
+
+    // Z block loads of this wave: block b = ks * ZK + d * CB + cb (k-step ks,
+    // digit d, 16-row block cb)
+    const int8_t *zsrc[R::LPW];
+    int zks[R::LPW];
+#pragma unroll
+    for (int u = 0; u < R::LPW; ++u) {
+        const int b = wave + u * R::NW;
+        zsrc[u] = zs.q;
+        zks[u] = 0;
+        if (b < R::ZB) {
+            const int ks = b / R::ZK, d = (b % R::ZK) / CB, cb = b % CB;
+            zks[u] = ks;
+            zsrc[u] = zs.q + ((int64_t)d * n_pad + k_base + cb * 16 + l16) * n_pad + 64 * ks + 16 * g;
+        }
+    }
+    auto issue = [&](int c) {
+        uint8_t *buf = lds + (c & 1) * (R::ZB * 1024);
+#pragma unroll
+        for (int u = 0; u < R::LPW; ++u) {
+            const int b = wave + u * R::NW;
+            if (b < R::ZB && c * KS + zks[u] < nk)
+                lds_dma16((const uint8_t *)(zsrc[u] + (int64_t)c * (64 * KS)), buf + b * 1024);
+        }
+    };
+    // genotype bytes of the wave's rows, samples 64 (c KS + ks) + 16 g .. + 15
+    // (zero past n or rows)
+    int64_t xrow[FM];
+#pragma unroll
+    for (int x = 0; x < FM; ++x) xrow[x] = i_base + wm * FM * 16 + x * 16 + l16;
+    const bool vec8 = (ldx % 8) == 0 && (((uintptr_t)X) % 8) == 0;
+    auto gload = [&](int c, uint4 (*v)[FM]) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int s0 = (c * KS + ks) * 64 + 16 * g;
+#pragma unroll
+            for (int x = 0; x < FM; ++x) {
+                const int64_t i = xrow[x];
+                const uint8_t *p = X + i * ldx + s0;
+                if (vec8 && i < rows && s0 + 16 <= n) {
+                    const uint2 lo = *(const uint2 *)p, hi = *(const uint2 *)(p + 8);
+                    v[ks][x] = make_uint4(lo.x, lo.y, hi.x, hi.y);
+                } else {
+                    uint32_t w[4] = {0, 0, 0, 0};
+                    if (i < rows)
+                        for (int e = 0; e < 16; ++e)
+                            if (s0 + e < n) w[e >> 2] |= (uint32_t)p[e] << (8 * (e & 3));
+                    v[ks][x] = make_uint4(w[0], w[1], w[2], w[3]);
+                }
+            }
+        }
+    };
+
+    i4v acc[ND][FM][FN];
+#pragma unroll
+    for (int d = 0; d < ND; ++d)
+#pragma unroll
+        for (int x = 0; x < FM; ++x)
+#pragma unroll
+            for (int y = 0; y < FN; ++y) acc[d][x][y] = i4v{0, 0, 0, 0};
+
+    uint4 xa[KS][FM], xn[KS][FM];
+    issue(0);
+    gload(0, xa);
+    const uint32_t zb0 = lds_addr(lds) + lane * 16 + wn * FN * 1024;
+    for (int c = 0; c < nst; ++c) {
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): stage c's Z blocks and genotypes are in
+        __syncthreads();                      // every wave's too; every wave has read stage c - 1
+        const bool more = c + 1 < nst;
+        if (more) {
+            issue(c + 1);
+            gload(c + 1, xn);
+        }
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            if (c * KS + ks >= nk) break;   // the tail of the last stage (wave-uniform)
+            i4v zf[R::NF];
+            lds_read_frags<R, 0, R::NF>(zf, zb0 + (c & 1) * (R::ZB * 1024) + ks * (R::ZK * 1024), 0);
+            i4v av[FM];
+#pragma unroll
+            for (int x = 0; x < FM; ++x)   // byte v -> signed v - 128
+                av[x] = i4v{(int)(xa[ks][x].x ^ 0x80808080u), (int)(xa[ks][x].y ^ 0x80808080u),
+                            (int)(xa[ks][x].z ^ 0x80808080u), (int)(xa[ks][x].w ^ 0x80808080u)};
+#pragma unroll
+            for (int d = 0; d < ND; ++d)
+#pragma unroll
+                for (int y = 0; y < FN; ++y)
+#pragma unroll
+                    for (int x = 0; x < FM; ++x)
+                        acc[d][x][y] =
+                            __builtin_amdgcn_mfma_i32_16x16x64_i8(av[x], zf[d * FN + y], acc[d][x][y], 0, 0, 0);
+        }
+        if (more) {
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                for (int x = 0; x < FM; ++x) xa[ks][x] = xn[ks][x];
+        }
+    }
+
+#pragma unroll
+    for (int y = 0; y < FN; ++y) {
+        const int k = k_base + wn * FN * 16 + y * 16 + l16;
+        const double off = zs.off[k], sc = zs.scale[k];
+#pragma unroll
+        for (int x = 0; x < FM; ++x)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = i_base + wm * FM * 16 + x * 16 + mfma16_row<false>(g, r);
+                double v = (double)acc[0][x][y][r];
+#pragma unroll
+                for (int d = 1; d < ND; ++d) v = fma(v, 256.0, (double)acc[d][x][y][r]);
+                if (i < rows) rot_store(out, i, k, (v + off) * sc);
+            }
+    }
+}
+
+// The same rotation with the genotypes staged through LDS as well, for
+// genotype rows whose stride, base address and length n are multiples of 4
+// bytes: both operands are loaded by direct global->LDS copies (the genotypes
+// 4 bytes per lane, 16 rows x 16 bytes per instruction; Z 16 bytes per lane)
+// into a ring of three stage buffers, two stages ahead of the MFMAs, and each
+// wave waits only for the stage it is about to read (every wave issues the
+// same number of copies per stage). Genotype words past n are loaded from the
+// row's start instead (any bytes do: they meet zero Z columns) and rows past
+// the range from the last row (their outputs are not stored).
+template <int WM_, int WN_, int FM_, int FN_>
+struct RotI8L {
+    static constexpr int WM = WM_, WN = WN_, FM = FM_, FN = FN_, ND = kZSlices;
+    static constexpr int NW = WM * WN, NT = 64 * NW;
+    static constexpr int TM = WM * FM * 16, TN = WN * FN * 16;
+    static constexpr int AB = TM / 16, CB = TN / 16;
+    static constexpr int SB = AB + ND * CB;              // blocks per stage: genotype blocks, then Z (digit-major)
+    static constexpr int NBUF = 3;
+    static constexpr int LDS = NBUF * SB * 1024;
+    static constexpr int AI = AB * 4 / NW;               // genotype copies per wave and stage (4 per block)
+    static constexpr int ZI = ND * CB / NW;              // Z copies per wave and stage
+    static constexpr int PER = AI + ZI;                  // copies per wave and stage
+    static constexpr int NF = FM + ND * FN;              // fragments per wave and stage: genotype x, then (digit, y)
+    static constexpr bool frag_is_b(int i) { return i >= FM; }
+    static constexpr int frag_off(int i) { return i < FM ? i * 1024 : (((i - FM) / FN) * CB + (i - FM) % FN) * 1024; }
+    static_assert(AB * 4 % NW == 0 && ND * CB % NW == 0, "every wave issues the same copies");
+    static_assert(PER < 64 && SB * 1024 <= 65536 && LDS <= 160 * 1024, "rotation stage too large");
+};
+
+using DefaultRotI8L = RotI8L<2, 4, 4, 1>;
+
+template <class R>
+__global__ __launch_bounds__(R::NT) void rotate_u8_i8_lds_kernel(const uint8_t *__restrict__ X, int64_t rows, int n,
+                                                                 int64_t ldx, ZSlices zs, int n_pad, RotOut out) {
+    constexpr int TN = R::TN, FM = R::FM, FN = R::FN, ND = R::ND, CB = R::CB, AB = R::AB;
+    extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
+    const int ntn = n_pad / TN;
+    const int64_t tile = tile_order(blockIdx.x, (rows + R::TM - 1) / R::TM, ntn);
+    const int tn = (int)(tile % ntn);
+    const int64_t tm = tile / ntn;
+    const int64_t i_base = tm * R::TM;
+    const int k_base = tn * TN;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave % R::WM, wn = wave / R::WM;
+    const int g = lane >> 4;
+    const int nst = (n + 63) / 64;   // stages of 64 samples; 64 nst <= n_pad
+
+    // genotype copy u of this wave: block rb = q / 4, part j = q % 4 (q = wave
+    // + u NW) fills LDS bytes [256 j, 256 j + 256) of the block, i.e. for lane
+    // l the word of row 16 rb + l / 4 at samples 16 j + 4 (l % 4) .. + 3
+    const uint8_t *asrc[R::AI];
+    int aoff[R::AI], adst[R::AI];
+#pragma unroll
+    for (int u = 0; u < R::AI; ++u) {
+        const int q = wave + u * R::NW, rb = q / 4, j = q % 4;
+        int64_t i = i_base + rb * 16 + lane / 4;
+        if (i >= rows) i = rows - 1;
+        asrc[u] = X + i * ldx;
+        aoff[u] = 16 * j + 4 * (lane % 4);
+        adst[u] = rb * 1024 + 256 * j;
+    }
+    // Z copy u: block b = d CB + cb holds for lane l the 16 bytes of digit d,
+    // row k0 + 16 cb + l % 16, samples 16 (l / 16) .. + 15
+    const int8_t *zsrc[R::ZI];
+    int zdst[R::ZI];
+#pragma unroll
+    for (int u = 0; u < R::ZI; ++u) {
+        const int b = wave + u * R::NW, d = b / CB, cb = b % CB;
+        zsrc[u] = zs.q + ((int64_t)d * n_pad + k_base + cb * 16 + (lane & 15)) * n_pad + 16 * g;
+        zdst[u] = (AB + b) * 1024;
+    }
+    auto issue = [&](int c) {
+        uint8_t *buf = lds + (c % R::NBUF) * (R::SB * 1024);
+#pragma unroll
+        for (int u = 0; u < R::AI; ++u) {
+            const int s = c * 64 + aoff[u];
+            lds_dma4(asrc[u] + (s < n ? s : 0), buf + adst[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < R::ZI; ++u) lds_dma16((const uint8_t *)(zsrc[u] + (int64_t)c * 64), buf + zdst[u]);
+    };
+
+    i4v acc[ND][FM][FN];
+#pragma unroll
+    for (int d = 0; d < ND; ++d)
+#pragma unroll
+        for (int x = 0; x < FM; ++x)
+#pragma unroll
+            for (int y = 0; y < FN; ++y) acc[d][x][y] = i4v{0, 0, 0, 0};
+
+    issue(0);
+    if (nst > 1) issue(1);
+    const uint32_t sa = lds_addr(lds) + lane * 16 + wm * FM * 1024;
+    const uint32_t sz = lds_addr(lds) + lane * 16 + (AB + wn * FN) * 1024;
+    for (int c = 0; c < nst; ++c) {
+        // this wave's copies of stage c landed; those of stage c + 1 may be in flight
+        if (c + 1 < nst) __builtin_amdgcn_s_waitcnt(vmcnt_imm(R::PER));
+        else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+        // every wave's copies too; every wave has read stage c - 1 (its reads
+        // waited for their data). A plain barrier: the fence of __syncthreads
+        // would wait for the copies of stage c + 1 as well.
+        __builtin_amdgcn_s_barrier();
+        if (c + 2 < nst) issue(c + 2);   // into the buffer of stage c - 1
+        const uint32_t so = (c % R::NBUF) * (R::SB * 1024);
+        i4v f[R::NF];
+        lds_read_frags<R, 0, R::NF>(f, sa + so, sz + so);
+        i4v av[FM];
+#pragma unroll
+        for (int x = 0; x < FM; ++x)   // byte v -> signed v - 128
+            av[x] = i4v{f[x][0] ^ (int)0x80808080u, f[x][1] ^ (int)0x80808080u, f[x][2] ^ (int)0x80808080u,
+                        f[x][3] ^ (int)0x80808080u};
+#pragma unroll
+        for (int d = 0; d < ND; ++d)
+#pragma unroll
+            for (int y = 0; y < FN; ++y)
+#pragma unroll
+                for (int x = 0; x < FM; ++x)
+                    acc[d][x][y] =
+                        __builtin_amdgcn_mfma_i32_16x16x64_i8(av[x], f[FM + d * FN + y], acc[d][x][y], 0, 0, 0);
+    }
+
+    const int l16 = lane & 15;
+#pragma unroll
+    for (int y = 0; y < FN; ++y) {
+        const int k = k_base + wn * FN * 16 + y * 16 + l16;
+        const double off = zs.off[k], sc = zs.scale[k];
+#pragma unroll
+        for (int x = 0; x < FM; ++x)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = i_base + wm * FM * 16 + x * 16 + mfma16_row<false>(g, r);
+                double v = (double)acc[0][x][y][r];
+#pragma unroll
+                for (int d = 1; d < ND; ++d) v = fma(v, 256.0, (double)acc[d][x][y][r]);
+                if (i < rows) rot_store(out, i, k, (v + off) * sc);
+            }
+    }
+}
+
 }  // namespace
+
+void slice_z_int8(const double *zh, int n_pad, int8_t *q, double *off, double *scale) {
+    const int64_t plane = (int64_t)n_pad * n_pad;
+    for (int k = 0; k < n_pad; ++k) {
+        const double *z = zh + (int64_t)k * n_pad;
+        double mx = 0.0;
+        for (int r = 0; r < n_pad; ++r) mx = std::max(mx, fabs(z[r]));
+        int e = 0;
+        frexp(mx, &e);                            // mx < 2^e
+        const int E = 8 * kZSlices - 2 - e;       // |z| 2^E < 2^(8 kZSlices - 2)
+        scale[k] = mx > 0.0 ? ldexp(1.0, -E) : 0.0;
+        __int128 sum = 0;
+        for (int r = 0; r < n_pad; ++r) {
+            int64_t v = mx > 0.0 ? llround(ldexp(z[r], E)) : 0;
+            sum += v;
+            for (int d = kZSlices - 1; d >= 1; --d) {   // balanced base-256 digits, low first
+                int64_t t = v & 255;
+                if (t >= 128) t -= 256;
+                q[d * plane + (int64_t)k * n_pad + r] = (int8_t)t;
+                v = (v - t) / 256;
+            }
+            q[(int64_t)k * n_pad + r] = (int8_t)v;      // |v| <= 65
+        }
+        off[k] = 128.0 * (double)sum;
+    }
+}
 
 template <class R>
 hipError_t launch_rotate_t(const void *X, int dtype, int64_t rows, int n, int64_t ldx, const double *Zrows,
@@ -364,8 +703,55 @@ hipError_t launch_rotate_u8_dma_t(const uint8_t *X, int64_t rows, int n, int64_t
     return hipGetLastError();
 }
 
+template <class R>
+hipError_t launch_rotate_u8_i8_t(const uint8_t *X, int64_t rows, int n, int64_t ldx, const ZSlices &zs, int n_pad,
+                                 const RotOut &out, hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    if (n_pad % R::TN || n_pad % 64 || n > n_pad || n_pad > kZSliceMaxNpad) return hipErrorInvalidValue;
+    const int64_t tiles = ((rows + R::TM - 1) / R::TM) * (n_pad / R::TN);
+    if (R::LDS > 65536) {
+        static bool attr_set = false;   // per instantiation
+        if (!attr_set) {
+            hipError_t e = hipFuncSetAttribute((const void *)rotate_u8_i8_kernel<R>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, R::LDS);
+            if (e != hipSuccess) return e;
+            attr_set = true;
+        }
+    }
+    hipLaunchKernelGGL((rotate_u8_i8_kernel<R>), dim3((unsigned)tiles), dim3(R::NT), R::LDS, s, X, rows, n, ldx, zs,
+                       n_pad, out);
+    return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_rotate_u8_i8_lds_t(const uint8_t *X, int64_t rows, int n, int64_t ldx, const ZSlices &zs,
+                                     int n_pad, const RotOut &out, hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    if (n_pad % R::TN || n_pad % 64 || n > n_pad || n_pad > kZSliceMaxNpad || n % 4 || ldx % 4 ||
+        ((uintptr_t)X) % 4)
+        return hipErrorInvalidValue;
+    const int64_t tiles = ((rows + R::TM - 1) / R::TM) * (n_pad / R::TN);
+    if (R::LDS > 65536) {
+        static bool attr_set = false;   // per instantiation
+        if (!attr_set) {
+            hipError_t e = hipFuncSetAttribute((const void *)rotate_u8_i8_lds_kernel<R>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, R::LDS);
+            if (e != hipSuccess) return e;
+            attr_set = true;
+        }
+    }
+    hipLaunchKernelGGL((rotate_u8_i8_lds_kernel<R>), dim3((unsigned)tiles), dim3(R::NT), R::LDS, s, X, rows, n, ldx,
+                       zs, n_pad, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_rotate(const void *X, int dtype, int64_t rows, int n, int64_t ldx, const double *Zrows,
-                         int n_pad, const RotOut &out, hipStream_t s) {
+                         int n_pad, const RotOut &out, hipStream_t s, const ZSlices *zs) {
+    if (dtype == GWAS_DT_U8 && zs && zs->q && n_pad <= kZSliceMaxNpad && n_pad % DefaultRotI8L::TN == 0 &&
+        n % 4 == 0 && ldx % 4 == 0 && ((uintptr_t)X) % 4 == 0)
+        return launch_rotate_u8_i8_lds_t<DefaultRotI8L>((const uint8_t *)X, rows, n, ldx, *zs, n_pad, out, s);
+    if (dtype == GWAS_DT_U8 && zs && zs->q && n_pad <= kZSliceMaxNpad && n_pad % DefaultRotI8::TN == 0)
+        return launch_rotate_u8_i8_t<DefaultRotI8>((const uint8_t *)X, rows, n, ldx, *zs, n_pad, out, s);
     if (dtype == GWAS_DT_U8)
         return launch_rotate_u8_dma_t<DefaultRotDma>((const uint8_t *)X, rows, n, ldx, Zrows, n_pad, out, s);
     return launch_rotate_t<DefaultRot>(X, dtype, rows, n, ldx, Zrows, n_pad, out, s);
