@@ -102,8 +102,12 @@ struct RotOut {
 // row's largest entry): with 6 digits below 1e-14 of x' for unit-norm rows.
 constexpr int kZSlices = 6;
 constexpr int kZSliceMaxNpad = 1 << 17;   // int32 headroom of the digit sums
+// The digits are stored in MFMA fragment order: 1 KB block (d, kb, s) =
+// ((d n_pad/16 + kb) n_pad/64 + s) holds at bytes 16 l .. 16 l + 15 digit d of
+// row 16 kb + l % 16, samples 64 s + 16 (l / 16) .. + 15, so a wave copies one
+// contiguous block per instruction.
 struct ZSlices {
-    const int8_t *q;       // [kZSlices][n_pad][n_pad]: digit d of row k at (d n_pad + k) n_pad
+    const int8_t *q;       // kZSlices n_pad^2 bytes in fragment order
     const double *off;     // [n_pad]: 128 sum_r q_k[r]
     const double *scale;   // [n_pad]: 2^-E_k (0 for an all-zero row)
 };

@@ -369,7 +369,7 @@ __global__ __launch_bounds__(R::NT) void rotate_u8_i8_kernel(const uint8_t *__re
         if (b < R::ZB) {
             const int ks = b / R::ZK, d = (b % R::ZK) / CB, cb = b % CB;
             zks[u] = ks;
-            zsrc[u] = zs.q + ((int64_t)d * n_pad + k_base + cb * 16 + l16) * n_pad + 64 * ks + 16 * g;
+            zsrc[u] = zs.q + (((int64_t)d * (n_pad / 16) + k_base / 16 + cb) * (n_pad / 64) + ks) * 1024 + 16 * lane;
         }
     }
     auto issue = [&](int c) {
@@ -378,7 +378,7 @@ __global__ __launch_bounds__(R::NT) void rotate_u8_i8_kernel(const uint8_t *__re
         for (int u = 0; u < R::LPW; ++u) {
             const int b = wave + u * R::NW;
             if (b < R::ZB && c * KS + zks[u] < nk)
-                lds_dma16((const uint8_t *)(zsrc[u] + (int64_t)c * (64 * KS)), buf + b * 1024);
+                lds_dma16((const uint8_t *)(zsrc[u] + (int64_t)c * (1024 * KS)), buf + b * 1024);
         }
     };
     // genotype bytes of the wave's rows, samples 64 (c KS + ks) + 16 g .. + 15
@@ -475,33 +475,40 @@ __global__ __launch_bounds__(R::NT) void rotate_u8_i8_kernel(const uint8_t *__re
 
 // The same rotation with the genotypes staged through LDS as well, for
 // genotype rows whose stride, base address and length n are multiples of 4
-// bytes: both operands are loaded by direct global->LDS copies (the genotypes
-// 4 bytes per lane, 16 rows x 16 bytes per instruction; Z 16 bytes per lane)
-// into a ring of three stage buffers, two stages ahead of the MFMAs, and each
-// wave waits only for the stage it is about to read (every wave issues the
-// same number of copies per stage). Genotype words past n are loaded from the
-// row's start instead (any bytes do: they meet zero Z columns) and rows past
-// the range from the last row (their outputs are not stored).
+// bytes: both operands are loaded by direct global->LDS copies into a ring of
+// three stage buffers, two stages ahead of the MFMAs, and each wave waits only
+// for the stage it is about to read (every wave issues the same number of
+// copies per stage). A genotype block is a 1 KB fragment block filled by
+// copies of 4 bytes per lane (16 rows x 16 bytes per instruction); a Z block
+// is one stored 1 KB block (one contiguous copy). Genotype words past n are
+// loaded from the row's start (any bytes do: they meet zero Z columns) and
+// rows past the range from the last row (their outputs are not stored). A
+// row-major genotype block at an 80-byte pitch (4 row segments per copy)
+// measured slower on MI355X: its 16-byte reads conflict on LDS banks.
 template <int WM_, int WN_, int FM_, int FN_>
 struct RotI8L {
     static constexpr int WM = WM_, WN = WN_, FM = FM_, FN = FN_, ND = kZSlices;
     static constexpr int NW = WM * WN, NT = 64 * NW;
     static constexpr int TM = WM * FM * 16, TN = WN * FN * 16;
     static constexpr int AB = TM / 16, CB = TN / 16;
-    static constexpr int SB = AB + ND * CB;              // blocks per stage: genotype blocks, then Z (digit-major)
+    static constexpr int ABYTES = 1024;                  // genotype block: one fragment block
+    static constexpr int SBYTES = AB * ABYTES + ND * CB * 1024;   // genotype blocks, then Z (digit-major)
     static constexpr int NBUF = 3;
-    static constexpr int LDS = NBUF * SB * 1024;
-    static constexpr int AI = AB * 4 / NW;               // genotype copies per wave and stage (4 per block)
+    static constexpr int LDS = NBUF * SBYTES;
+    static constexpr int AI = AB * (ABYTES / 256) / NW;  // genotype copies per wave and stage (256 B each)
     static constexpr int ZI = ND * CB / NW;              // Z copies per wave and stage
     static constexpr int PER = AI + ZI;                  // copies per wave and stage
     static constexpr int NF = FM + ND * FN;              // fragments per wave and stage: genotype x, then (digit, y)
     static constexpr bool frag_is_b(int i) { return i >= FM; }
-    static constexpr int frag_off(int i) { return i < FM ? i * 1024 : (((i - FM) / FN) * CB + (i - FM) % FN) * 1024; }
-    static_assert(AB * 4 % NW == 0 && ND * CB % NW == 0, "every wave issues the same copies");
-    static_assert(PER < 64 && SB * 1024 <= 65536 && LDS <= 160 * 1024, "rotation stage too large");
+    static constexpr int frag_off(int i) {
+        return i < FM ? i * ABYTES : (((i - FM) / FN) * CB + (i - FM) % FN) * 1024;
+    }
+    static_assert(ABYTES % 256 == 0 && AB * (ABYTES / 256) % NW == 0 && ND * CB % NW == 0,
+                  "every wave issues the same copies");
+    static_assert(PER < 64 && SBYTES <= 65536 && LDS <= 160 * 1024, "rotation stage too large");
 };
 
-using DefaultRotI8L = RotI8L<2, 4, 4, 1>;
+using DefaultRotI8L = RotI8L<2, 2, 4, 1>;
 
 template <class R>
 __global__ __launch_bounds__(R::NT) void rotate_u8_i8_lds_kernel(const uint8_t *__restrict__ X, int64_t rows, int n,
@@ -522,9 +529,9 @@ __global__ __launch_bounds__(R::NT) void rotate_u8_i8_lds_kernel(const uint8_t *
     const int g = lane >> 4;
     const int nst = (n + 63) / 64;   // stages of 64 samples; 64 nst <= n_pad
 
-    // genotype copy u of this wave: block rb = q / 4, part j = q % 4 (q = wave
-    // + u NW) fills LDS bytes [256 j, 256 j + 256) of the block, i.e. for lane
-    // l the word of row 16 rb + l / 4 at samples 16 j + 4 (l % 4) .. + 3
+    // genotype copy u of this wave: part j of block rb (q = wave + u NW,
+    // rb = q / 4, j = q % 4) fills block bytes [256 j, 256 j + 256), i.e. for
+    // lane l the word of row 16 rb + l / 4 at samples 16 j + 4 (l % 4) .. + 3
     const uint8_t *asrc[R::AI];
     int aoff[R::AI], adst[R::AI];
 #pragma unroll
@@ -534,27 +541,27 @@ __global__ __launch_bounds__(R::NT) void rotate_u8_i8_lds_kernel(const uint8_t *
         if (i >= rows) i = rows - 1;
         asrc[u] = X + i * ldx;
         aoff[u] = 16 * j + 4 * (lane % 4);
-        adst[u] = rb * 1024 + 256 * j;
+        adst[u] = rb * R::ABYTES + 256 * j;
     }
     // Z copy u: block b = d CB + cb holds for lane l the 16 bytes of digit d,
-    // row k0 + 16 cb + l % 16, samples 16 (l / 16) .. + 15
+    // row k0 + 16 cb + l % 16, samples 16 (l / 16) .. + 15 (one stored block)
     const int8_t *zsrc[R::ZI];
     int zdst[R::ZI];
 #pragma unroll
     for (int u = 0; u < R::ZI; ++u) {
         const int b = wave + u * R::NW, d = b / CB, cb = b % CB;
-        zsrc[u] = zs.q + ((int64_t)d * n_pad + k_base + cb * 16 + (lane & 15)) * n_pad + 16 * g;
-        zdst[u] = (AB + b) * 1024;
+        zsrc[u] = zs.q + ((int64_t)d * (n_pad / 16) + k_base / 16 + cb) * (n_pad / 64) * 1024 + 16 * lane;
+        zdst[u] = AB * R::ABYTES + b * 1024;
     }
     auto issue = [&](int c) {
-        uint8_t *buf = lds + (c % R::NBUF) * (R::SB * 1024);
+        uint8_t *buf = lds + (c % R::NBUF) * R::SBYTES;
 #pragma unroll
         for (int u = 0; u < R::AI; ++u) {
             const int s = c * 64 + aoff[u];
             lds_dma4(asrc[u] + (s < n ? s : 0), buf + adst[u]);
         }
 #pragma unroll
-        for (int u = 0; u < R::ZI; ++u) lds_dma16((const uint8_t *)(zsrc[u] + (int64_t)c * 64), buf + zdst[u]);
+        for (int u = 0; u < R::ZI; ++u) lds_dma16((const uint8_t *)(zsrc[u] + (int64_t)c * 1024), buf + zdst[u]);
     };
 
     i4v acc[ND][FM][FN];
@@ -567,8 +574,8 @@ __global__ __launch_bounds__(R::NT) void rotate_u8_i8_lds_kernel(const uint8_t *
 
     issue(0);
     if (nst > 1) issue(1);
-    const uint32_t sa = lds_addr(lds) + lane * 16 + wm * FM * 1024;
-    const uint32_t sz = lds_addr(lds) + lane * 16 + (AB + wn * FN) * 1024;
+    const uint32_t sa = lds_addr(lds) + lane * 16 + wm * FM * R::ABYTES;
+    const uint32_t sz = lds_addr(lds) + lane * 16 + AB * R::ABYTES + wn * FN * 1024;
     for (int c = 0; c < nst; ++c) {
         // this wave's copies of stage c landed; those of stage c + 1 may be in flight
         if (c + 1 < nst) __builtin_amdgcn_s_waitcnt(vmcnt_imm(R::PER));
@@ -578,7 +585,7 @@ __global__ __launch_bounds__(R::NT) void rotate_u8_i8_lds_kernel(const uint8_t *
         // would wait for the copies of stage c + 1 as well.
         __builtin_amdgcn_s_barrier();
         if (c + 2 < nst) issue(c + 2);   // into the buffer of stage c - 1
-        const uint32_t so = (c % R::NBUF) * (R::SB * 1024);
+        const uint32_t so = (c % R::NBUF) * R::SBYTES;
         i4v f[R::NF];
         lds_read_frags<R, 0, R::NF>(f, sa + so, sz + so);
         i4v av[FM];
@@ -617,7 +624,11 @@ __global__ __launch_bounds__(R::NT) void rotate_u8_i8_lds_kernel(const uint8_t *
 }  // namespace
 
 void slice_z_int8(const double *zh, int n_pad, int8_t *q, double *off, double *scale) {
-    const int64_t plane = (int64_t)n_pad * n_pad;
+    // byte of digit d, row k, sample r in fragment order (see ZSlices)
+    auto at = [&](int d, int k, int r) -> int8_t & {
+        const int64_t blk = ((int64_t)d * (n_pad / 16) + k / 16) * (n_pad / 64) + r / 64;
+        return q[blk * 1024 + 16 * ((k % 16) + 16 * ((r % 64) / 16)) + r % 16];
+    };
     for (int k = 0; k < n_pad; ++k) {
         const double *z = zh + (int64_t)k * n_pad;
         double mx = 0.0;
@@ -633,10 +644,10 @@ void slice_z_int8(const double *zh, int n_pad, int8_t *q, double *off, double *s
             for (int d = kZSlices - 1; d >= 1; --d) {   // balanced base-256 digits, low first
                 int64_t t = v & 255;
                 if (t >= 128) t -= 256;
-                q[d * plane + (int64_t)k * n_pad + r] = (int8_t)t;
+                at(d, k, r) = (int8_t)t;
                 v = (v - t) / 256;
             }
-            q[(int64_t)k * n_pad + r] = (int8_t)v;      // |v| <= 65
+            at(0, k, r) = (int8_t)v;                    // |v| <= 65
         }
         off[k] = 128.0 * (double)sum;
     }
