@@ -2,7 +2,8 @@
 
 A step is one pass of the whole hot path over the paper-shape workload
 (n = 1000 samples, p = 4, m = 100,000 SNPs, t = 1,000 traits, synthetic data
-drawn by `synth`): rotation of every SNP by Z^T (FP64 MFMA GEMM) and the solve
+drawn by `synth`): rotation of every SNP by Z^T (genotype bytes on the int8 MFMAs against Z in
+int8 digits, exact integer sums) and the solve
 of the 10^8-problem grid (trait rotation, per-trait prologue, fused
 contraction + FP64 p x p solve), with b left in HBM. Inputs (genotypes as
 uint8, traits as FP64) are resident in HBM before timing starts; the host

@@ -169,146 +169,6 @@ __global__ __launch_bounds__(R::NT) void rotate_kernel(const Tin *__restrict__ X
 }
 
 
-// Genotype rotation with Z staged by direct global->LDS loads.
-//
-// A stage covers 64 samples. Lane group g of a wave owns samples
-// 16 g .. 16 g + 15 of the stage: its 16 genotype bytes of each of the wave's
-// SNP rows come straight from global memory into registers (prefetched one
-// stage ahead) and are widened to FP64 one sample per MFMA. Z is staged in two
-// LDS buffers of 1 KB blocks: block (k-block cb, pair h) holds, for lane l,
-// Z[k0 + 16 cb + l % 16][s0 + 16 (l / 16) + 2 h + {0, 1}], the two samples that
-// MFMAs 2h and 2h+1 of lane group l / 16 pair with its genotypes. The next
-// stage's Z loads run while this stage's fragments are read and multiplied.
-template <int WM_, int WN_, int FM_, int FN_>
-struct RotDma {
-    static constexpr int WM = WM_, WN = WN_, FM = FM_, FN = FN_;
-    static constexpr int NW = WM * WN, NT = 64 * NW;
-    static constexpr int TM = WM * FM * 16, TN = WN * FN * 16;
-    static constexpr int ZB = (TN / 16) * 8;            // Z blocks per stage
-    static constexpr int LDS = 2 * ZB * 1024;
-    static constexpr int LPW = (ZB + NW - 1) / NW;      // Z block loads per wave and stage
-    static constexpr int NF = FN * 8;                   // Z fragments a wave reads per stage
-    static constexpr bool frag_is_b(int) { return false; }
-    static constexpr int frag_off(int i) { return i * 1024; }   // from the wave's first block
-    static_assert(ZB * 1024 <= 65536 && LDS <= 160 * 1024, "rotation stage too large");
-};
-
-using DefaultRotDma = RotDma<8, 1, 1, 2>;   // fastest of a tile sweep on MI355X (n = 1000)
-
-template <class R>
-__global__ __launch_bounds__(R::NT) void rotate_u8_dma_kernel(const uint8_t *__restrict__ X, int64_t rows, int n,
-                                                              int64_t ldx, const double *__restrict__ Zr, int n_pad,
-                                                              RotOut out) {
-    constexpr int TN = R::TN, FM = R::FM, FN = R::FN;
-    extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
-    const int ntn = n_pad / TN;
-    const int64_t tile = tile_order(blockIdx.x, (rows + R::TM - 1) / R::TM, ntn);
-    const int tn = (int)(tile % ntn);
-    const int64_t tm = tile / ntn;
-    const int64_t i_base = tm * R::TM;
-    const int k_base = tn * TN;
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wm = wave % R::WM, wn = wave / R::WM;
-    const int l16 = lane & 15, g = lane >> 4;
-    const int nst = (n + 63) / 64;   // stages; 64 * nst <= n_pad
-
-    // Z block loads of this wave: block b = cb * 8 + h
-    const uint8_t *zsrc[R::LPW];
-#pragma unroll
-    for (int u = 0; u < R::LPW; ++u) {
-        const int b = wave + u * R::NW;
-        const int cb = b / 8, h = b % 8;
-        zsrc[u] = (const uint8_t *)(Zr + (int64_t)(k_base + cb * 16 + l16) * n_pad + 16 * g + 2 * h);
-    }
-    auto issue = [&](int c) {
-        uint8_t *buf = lds + (c & 1) * (R::ZB * 1024);
-#pragma unroll
-        for (int u = 0; u < R::LPW; ++u) {
-            const int b = wave + u * R::NW;
-            if (b < R::ZB) lds_dma16(zsrc[u] + (int64_t)c * 64 * 8, buf + b * 1024);
-        }
-    };
-    // genotype bytes of the wave's rows, samples 64 c + 16 g .. + 15 (zero past n or rows)
-    int64_t xrow[FM];
-#pragma unroll
-    for (int x = 0; x < FM; ++x) xrow[x] = i_base + wm * FM * 16 + x * 16 + l16;
-    const bool vec8 = (ldx % 8) == 0 && (((uintptr_t)X) % 8) == 0;
-    auto gload = [&](int c, uint4 *v) {
-        const int s0 = c * 64 + 16 * g;
-#pragma unroll
-        for (int x = 0; x < FM; ++x) {
-            const int64_t i = xrow[x];
-            const uint8_t *p = X + i * ldx + s0;
-            if (vec8 && i < rows && s0 + 16 <= n) {
-                const uint2 lo = *(const uint2 *)p, hi = *(const uint2 *)(p + 8);
-                v[x] = make_uint4(lo.x, lo.y, hi.x, hi.y);
-            } else {
-                uint32_t w[4] = {0, 0, 0, 0};
-                if (i < rows)
-                    for (int e = 0; e < 16; ++e)
-                        if (s0 + e < n) w[e >> 2] |= (uint32_t)p[e] << (8 * (e & 3));
-                v[x] = make_uint4(w[0], w[1], w[2], w[3]);
-            }
-        }
-    };
-
-    d4 acc[FM][FN];
-#pragma unroll
-    for (int a = 0; a < FM; ++a)
-#pragma unroll
-        for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-
-    uint4 xa[FM], xn[FM];
-    issue(0);
-    gload(0, xa);
-    const uint32_t zb0 = lds_addr(lds) + lane * 16 + wn * FN * 8 * 1024;
-    for (int c = 0; c < nst; ++c) {
-        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): stage c's Z blocks and genotypes are in
-        __syncthreads();                      // every wave's too; every wave has read stage c - 1
-        const bool more = c + 1 < nst;
-        if (more) {
-            issue(c + 1);
-            gload(c + 1, xn);
-        }
-        i4v zf[R::NF];
-        lds_read_frags<R, 0, R::NF>(zf, zb0 + (c & 1) * (R::ZB * 1024), 0);
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            double xv[FM];
-#pragma unroll
-            for (int a = 0; a < FM; ++a) {
-                const uint32_t word = e < 4 ? xa[a].x : e < 8 ? xa[a].y : e < 12 ? xa[a].z : xa[a].w;
-                xv[a] = (double)((word >> (8 * (e & 3))) & 0xffu);
-            }
-#pragma unroll
-            for (int b = 0; b < FN; ++b) {
-                const double2 z2 = __builtin_bit_cast(double2, zf[b * 8 + e / 2]);
-                const double zv = (e & 1) ? z2.y : z2.x;
-#pragma unroll
-                for (int a = 0; a < FM; ++a)
-                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[a], zv, acc[a][b], 0, 0, 0);
-            }
-        }
-        if (more) {
-#pragma unroll
-            for (int a = 0; a < FM; ++a) xa[a] = xn[a];
-        }
-    }
-
-#pragma unroll
-    for (int a = 0; a < FM; ++a)
-#pragma unroll
-        for (int b = 0; b < FN; ++b)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t i = i_base + wm * FM * 16 + a * 16 + mfma16_row<true>(g, r);
-                const int k = k_base + wn * FN * 16 + b * 16 + l16;
-                if (i < rows) rot_store(out, i, k, acc[a][b][r]);
-            }
-}
-
 // Genotype rotation on the int8 MFMAs (v_mfma_i32_16x16x64_i8) with Z sliced
 // into int8 digits (ZSlices). A stage covers KS k-steps of 64 samples. In
 // k-step ks, lane group g of a wave holds samples 16 g .. 16 g + 15 of each of
@@ -695,26 +555,6 @@ hipError_t launch_rotate_t(const void *X, int dtype, int64_t rows, int n, int64_
 }
 
 template <class R>
-hipError_t launch_rotate_u8_dma_t(const uint8_t *X, int64_t rows, int n, int64_t ldx, const double *Zrows,
-                                  int n_pad, const RotOut &out, hipStream_t s) {
-    if (rows <= 0) return hipSuccess;
-    if (n_pad % R::TN || n_pad % 64 || n > n_pad) return hipErrorInvalidValue;
-    const int64_t tiles = ((rows + R::TM - 1) / R::TM) * (n_pad / R::TN);
-    if (R::LDS > 65536) {
-        static bool attr_set = false;   // per instantiation
-        if (!attr_set) {
-            hipError_t e = hipFuncSetAttribute((const void *)rotate_u8_dma_kernel<R>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, R::LDS);
-            if (e != hipSuccess) return e;
-            attr_set = true;
-        }
-    }
-    hipLaunchKernelGGL((rotate_u8_dma_kernel<R>), dim3((unsigned)tiles), dim3(R::NT), R::LDS, s, X, rows, n, ldx,
-                       Zrows, n_pad, out);
-    return hipGetLastError();
-}
-
-template <class R>
 hipError_t launch_rotate_u8_i8_t(const uint8_t *X, int64_t rows, int n, int64_t ldx, const ZSlices &zs, int n_pad,
                                  const RotOut &out, hipStream_t s) {
     if (rows <= 0) return hipSuccess;
@@ -763,8 +603,6 @@ hipError_t launch_rotate(const void *X, int dtype, int64_t rows, int n, int64_t 
         return launch_rotate_u8_i8_lds_t<DefaultRotI8L>((const uint8_t *)X, rows, n, ldx, *zs, n_pad, out, s);
     if (dtype == GWAS_DT_U8 && zs && zs->q && n_pad <= kZSliceMaxNpad && n_pad % DefaultRotI8::TN == 0)
         return launch_rotate_u8_i8_t<DefaultRotI8>((const uint8_t *)X, rows, n, ldx, *zs, n_pad, out, s);
-    if (dtype == GWAS_DT_U8)
-        return launch_rotate_u8_dma_t<DefaultRotDma>((const uint8_t *)X, rows, n, ldx, Zrows, n_pad, out, s);
     return launch_rotate_t<DefaultRot>(X, dtype, rows, n, ldx, Zrows, n_pad, out, s);
 }
 
