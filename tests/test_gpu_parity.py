@@ -79,6 +79,48 @@ def test_rotate_dtypes_and_device_input(tiny, dtype, torch_cuda):
     c.close()
 
 
+@pytest.mark.parametrize("n,m,shift", [(1000, 300, 0), (333, 257, 0), (1000, 300, 1), (64, 17, 0)])
+def test_genotype_rotation_full_byte_range(n, m, shift, torch_cuda):
+    """Genotype bytes over the whole range 0..255 (the int8 kernels offset them
+    to v - 128 and sum exact int32 digit products): every rotated value against
+    the FP64 product. n = 1000 takes the LDS-staged kernel; n = 333, and rows
+    starting at an odd device address (shift = 1), the register-staged one."""
+    torch = torch_cuda
+    phi, xl, _, _, _ = synth.small(n, 3, 1, 1, seed=n + shift)
+    xr = np.random.default_rng(n + m).integers(0, 256, size=(m, n), dtype=np.uint8)
+    xr[0] = 255                       # extreme rows
+    xr[1] = 0
+    w, z = np.linalg.eigh(phi)
+    from paper_1210_7683_amd import gwas
+    c = gwas.Cohort(z, w, xl, m, forms=("f64", "f32"))
+    buf = torch.zeros(m * n + shift, dtype=torch.uint8, device="cuda")
+    dev = buf[shift:].view(m, n)
+    dev.copy_(torch.from_numpy(xr))
+    assert dev.data_ptr() % 4 == shift
+    c.rotate(0, dev)
+    torch.cuda.synchronize()
+    ref = xr.astype(np.float64) @ z
+    got = c.copy_rotated(0, m, "f64")
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print("n=%d m=%d shift=%d: max |rotated - FP64 product| / max = %.2e" % (n, m, shift, err))
+    assert err <= 1e-12
+    assert np.array_equal(c.copy_rotated(0, m, "f32"), got.astype(np.float32))
+    c.close()
+
+
+@pytest.mark.parametrize("form", ["f64", "f32"])
+def test_full_byte_range_genotypes_solve_against_oracle(form, torch_cuda):
+    """b for genotype bytes over 0..255 (dosages scaled to a byte, say) against
+    the oracle, at the form's bound."""
+    phi, xl, _, y, h2 = synth.small(200, 4, 1, 6, seed=17)
+    xr = np.random.default_rng(18).integers(0, 256, size=(150, 200), dtype=np.uint8)
+    ref = oracle.gls_grid(phi, xl, xr, y, h2)
+    c = cohort(phi, xl, xr, forms=(form,))
+    b = c.solve(y, h2, form=form).cpu().numpy()
+    c.close()
+    assert scaled_err(b, ref).max() <= TOL[form]
+
+
 @pytest.mark.parametrize("n,m", [(77, 129), (200, 333), (1000, 300)])
 def test_genotype_rotation_ragged_n_and_rows(n, m, torch_cuda):
     """uint8 genotypes with n not a multiple of the 64-sample stage (and, for
