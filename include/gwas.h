@@ -104,6 +104,28 @@ typedef struct gwas_stats_t {
 void gwas_default_options(gwas_options *opt);
 
 /*
+ * Eigendecomposition of the kinship matrix on the device, for setup (the
+ * eigendecomposition before the loops of Algorithm 5; Section 3.1):
+ * Phi = Z diag(w) Z^T in FP64, by Householder tridiagonalisation and divide and
+ * conquer (rocSOLVER dsyevd, loaded on the first call; not on the solve path).
+ *   n          1 <= n <= 16384
+ *   Phi        n x n symmetric FP64, column-major; only its lower triangle is read
+ *   Z          out: n x n column-major, column k = unit eigenvector k (the layout
+ *              gwas_setup takes)
+ *   w          out: the n eigenvalues, ascending
+ *   on_device  nonzero: Phi, Z and w are device memory of the current device;
+ *              zero: host memory
+ *   stream     HIP stream for the device work (NULL: the default stream)
+ * Phi and Z may be the same buffer. Temporary device memory of about
+ * 8 n^2 bytes is allocated and freed. Synchronous: returns once Z and w hold
+ * the result.
+ * Errors: GWAS_EINVAL (n out of range, NULL pointers), GWAS_ENOMEM, GWAS_EHIP
+ * (runtime failure, solver library not found, or no convergence; the message
+ * of gwas_last_error says which).
+ */
+gwas_status gwas_eigh(int32_t n, const double *Phi, double *Z, double *w, int32_t on_device, void *stream);
+
+/*
  * Create a context: upload the eigendecomposition of the kinship matrix and
  * the covariates, rotate the covariates (Algorithm 5, preloop: X'_L = Z^T X_L,
  * in FP64), and allocate the resident rotated-SNP store for m_capacity SNPs in

@@ -98,6 +98,8 @@ def load():
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     lib.gwas_default_options.argtypes = [ctypes.POINTER(Options)]
     lib.gwas_default_options.restype = None
+    lib.gwas_eigh.argtypes = [i32, vp, vp, vp, i32, vp]
+    lib.gwas_eigh.restype = i32
     lib.gwas_setup.argtypes = [ctypes.POINTER(vp), i32, i32, vp, vp, vp, ctypes.POINTER(Options)]
     lib.gwas_setup.restype = i32
     lib.gwas_rotate.argtypes = [vp, i64, i64, vp, i32, i32, vp]
@@ -496,6 +498,33 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def eigh(phi, stream=None):
+    """Eigendecomposition of the symmetric kinship matrix on the GPU (gwas_eigh),
+    in numpy.linalg.eigh's convention: (w ascending, Z with column k the unit
+    eigenvector k). A torch CUDA tensor gives CUDA tensors back (FP64); anything
+    else is taken as a host array and numpy arrays come back."""
+    if _is_device(phi):
+        import torch
+        a = phi.to(torch.float64).contiguous()
+        n = a.shape[0]
+        if a.shape != (n, n):
+            raise ValueError("Phi must be square")
+        z = torch.empty_like(a)
+        w = torch.empty(n, dtype=torch.float64, device=a.device)
+        # column-major Phi is Phi itself (symmetric); column-major Z is Z^T row-major
+        _check(load().gwas_eigh(n, a.data_ptr(), z.data_ptr(), w.data_ptr(), 1, _stream_ptr(stream)))
+        return w, z.T.contiguous()
+    a = np.ascontiguousarray(phi, dtype=np.float64)
+    n = a.shape[0]
+    if a.shape != (n, n):
+        raise ValueError("Phi must be square")
+    zc = np.empty((n, n), dtype=np.float64)
+    w = np.empty(n, dtype=np.float64)
+    st = load().gwas_eigh(n, a.ctypes.data, zc.ctypes.data, w.ctypes.data, 0, None)
+    _check(st)
+    return w, np.ascontiguousarray(zc.T)
 
 
 def clock() -> float:

@@ -59,3 +59,26 @@ def test_setup_rejects_fold_intervals_other_than_0_and_2(bad):
     xl = np.ones((1, n))
     with pytest.raises(gwas.GwasError, match="f32_flush"):
         gwas.Cohort(z, w, xl, 4, forms=("f32",), f32_flush=bad)
+
+
+@pytest.mark.parametrize("n", [0, -3, 16385])
+def test_eigh_rejects_sizes_out_of_range(n):
+    """gwas_eigh checks n before it opens the solver or touches a device."""
+    import numpy as np
+
+    from paper_1210_7683_amd import gwas
+    lib = gwas.load()
+    z = np.zeros(4)
+    w = np.zeros(2)
+    st = lib.gwas_eigh(n, z.ctypes.data, z.ctypes.data, w.ctypes.data, 0, None)
+    assert st == gwas.EINVAL
+    assert "outside" in lib.gwas_last_error().decode()
+
+
+def test_eigh_rejects_null_pointers():
+    import numpy as np
+
+    from paper_1210_7683_amd import gwas
+    lib = gwas.load()
+    w = np.zeros(2)
+    assert lib.gwas_eigh(2, None, None, w.ctypes.data, 0, None) == gwas.EINVAL
