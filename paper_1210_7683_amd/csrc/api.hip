@@ -185,7 +185,7 @@ gwas_status gwas_setup(gwas_ctx **out, int32_t n, int32_t p, const double *Z, co
     TRY(dalloc(c, &c->Z, sizeof(double) * np * np));
     if (np <= kZSliceMaxNpad) {
         TRY(dalloc(c, &c->zq, (size_t)kZSlices * np * np));
-        TRY(dalloc(c, &c->zoff, sizeof(double) * np));
+        TRY(dalloc(c, &c->zoff, sizeof(double) * 2 * np));
         TRY(dalloc(c, &c->zscale, sizeof(double) * np));
     }
     TRY(dalloc(c, &c->w, sizeof(double) * np));
@@ -217,10 +217,10 @@ gwas_status gwas_setup(gwas_ctx **out, int32_t n, int32_t p, const double *Z, co
         hipError_t e = hipMemcpy(c->Z, zh, sizeof(double) * np * np, hipMemcpyHostToDevice);
         if (e == hipSuccess && c->zq) {   // int8 digits of Z for the genotype rotation
             std::vector<int8_t> q((size_t)kZSlices * np * np);
-            std::vector<double> off(np), sc(np);
+            std::vector<double> off(2 * (size_t)np), sc(np);
             slice_z_int8(zh, np, q.data(), off.data(), sc.data());
             e = hipMemcpy(c->zq, q.data(), q.size(), hipMemcpyHostToDevice);
-            if (e == hipSuccess) e = hipMemcpy(c->zoff, off.data(), sizeof(double) * np, hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipMemcpy(c->zoff, off.data(), sizeof(double) * 2 * np, hipMemcpyHostToDevice);
             if (e == hipSuccess) e = hipMemcpy(c->zscale, sc.data(), sizeof(double) * np, hipMemcpyHostToDevice);
         }
         free(zh);

@@ -88,7 +88,7 @@ struct gwas_ctx {
 
     double *Z = nullptr;     // [n_pad][n_pad]: row k = eigenvector k (zeros beyond n)
     int8_t *zq = nullptr;    // int8 digits of Z for the genotype rotation (ZSlices)
-    double *zoff = nullptr, *zscale = nullptr;   // [n_pad] each
+    double *zoff = nullptr, *zscale = nullptr;   // [2][n_pad] and [n_pad]
     double *w = nullptr;     // [n_pad]
     double *xlt = nullptr;   // [p-1][n_pad]
     double *xr64 = nullptr;  // [m_rows][n_pad]

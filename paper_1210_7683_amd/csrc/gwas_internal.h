@@ -100,7 +100,12 @@ struct RotOut {
 //   x'[k] = 2^-E_k (sum_d 256^(kZSlices-1-d) acc_d + 128 sum_r q_k[r]).
 // The only error is the rounding of Z to 8 kZSlices - 1 bits (relative to the
 // row's largest entry): with 6 digits below 1e-14 of x' for unit-norm rows.
+// Rotations that fill no FP64 store use only the leading kZSlicesShort digits
+// (Z to about 2^-30 of its row maximum, far below FP32 rounding): the
+// truncated integer q'_k = sum_{d < kZSlicesShort} 256^(kZSlicesShort-1-d) s_d
+// stands for 2^-(E_k - 8 (kZSlices - kZSlicesShort)) q'_k.
 constexpr int kZSlices = 6;
+constexpr int kZSlicesShort = 4;
 constexpr int kZSliceMaxNpad = 1 << 17;   // int32 headroom of the digit sums
 // The digits are stored in MFMA fragment order: 1 KB block (d, kb, s) =
 // ((d n_pad/16 + kb) n_pad/64 + s) holds at bytes 16 l .. 16 l + 15 digit d of
@@ -108,7 +113,7 @@ constexpr int kZSliceMaxNpad = 1 << 17;   // int32 headroom of the digit sums
 // contiguous block per instruction.
 struct ZSlices {
     const int8_t *q;       // kZSlices n_pad^2 bytes in fragment order
-    const double *off;     // [n_pad]: 128 sum_r q_k[r]
+    const double *off;     // [2][n_pad]: 128 sum_r q_k[r], then 128 sum_r q'_k[r]
     const double *scale;   // [n_pad]: 2^-E_k (0 for an all-zero row)
 };
 // Host: slices of the padded row-major Z (row k = eigenvector k, zeros past n).

@@ -14,6 +14,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "gwas_internal.h"
 #include "lds_dma.h"
@@ -179,9 +180,9 @@ __global__ __launch_bounds__(R::NT) void rotate_kernel(const Tin *__restrict__ X
 // SNP block, Z block) and k-step; the digit sums are exact int32, recombined
 // in FP64 by the epilogue. The next stage's Z blocks and genotypes load under
 // the MFMAs; k-steps at or past n_pad (the tail of the last stage) are skipped.
-template <int WM_, int WN_, int FM_, int FN_, int KS_ = 1>
+template <int WM_, int WN_, int FM_, int FN_, int KS_ = 1, int ND_ = kZSlices>
 struct RotI8 {
-    static constexpr int WM = WM_, WN = WN_, FM = FM_, FN = FN_, KS = KS_, ND = kZSlices;
+    static constexpr int WM = WM_, WN = WN_, FM = FM_, FN = FN_, KS = KS_, ND = ND_;   // ND leading digits
     static constexpr int NW = WM * WN, NT = 64 * NW;
     static constexpr int TM = WM * FM * 16, TN = WN * FN * 16;
     static constexpr int CB = TN / 16;                  // 16-row Z blocks of the tile
@@ -195,7 +196,8 @@ struct RotI8 {
     static_assert(ZK * 1024 <= 65536 && LDS <= 160 * 1024, "rotation stage too large");
 };
 
-using DefaultRotI8 = RotI8<4, 2, 2, 1>;
+template <int ND>
+using DefaultRotI8 = RotI8<4, 2, 2, 1, 1, ND>;
 
 template <class R>
 __global__ __launch_bounds__(R::NT) void rotate_u8_i8_kernel(const uint8_t *__restrict__ X, int64_t rows, int n,
@@ -319,7 +321,9 @@ __global__ __launch_bounds__(R::NT) void rotate_u8_i8_kernel(const uint8_t *__re
 #pragma unroll
     for (int y = 0; y < FN; ++y) {
         const int k = k_base + wn * FN * 16 + y * 16 + l16;
-        const double off = zs.off[k], sc = zs.scale[k];
+        // ND leading digits: the offset of their sum, and 2^-E_k times 256^(kZSlices - ND)
+        const double off = zs.off[(ND == kZSlices ? 0 : n_pad) + k];
+        const double sc = zs.scale[k] * (double)(1ull << (8 * (kZSlices - ND)));
 #pragma unroll
         for (int x = 0; x < FM; ++x)
 #pragma unroll
@@ -345,9 +349,9 @@ __global__ __launch_bounds__(R::NT) void rotate_u8_i8_kernel(const uint8_t *__re
 // rows past the range from the last row (their outputs are not stored). A
 // row-major genotype block at an 80-byte pitch (4 row segments per copy)
 // measured slower on MI355X: its 16-byte reads conflict on LDS banks.
-template <int WM_, int WN_, int FM_, int FN_>
+template <int WM_, int WN_, int FM_, int FN_, int ND_ = kZSlices>
 struct RotI8L {
-    static constexpr int WM = WM_, WN = WN_, FM = FM_, FN = FN_, ND = kZSlices;
+    static constexpr int WM = WM_, WN = WN_, FM = FM_, FN = FN_, ND = ND_;   // ND leading digits
     static constexpr int NW = WM * WN, NT = 64 * NW;
     static constexpr int TM = WM * FM * 16, TN = WN * FN * 16;
     static constexpr int AB = TM / 16, CB = TN / 16;
@@ -368,7 +372,11 @@ struct RotI8L {
     static_assert(PER < 64 && SBYTES <= 65536 && LDS <= 160 * 1024, "rotation stage too large");
 };
 
-using DefaultRotI8L = RotI8L<2, 2, 4, 1>;
+// fastest of sweeps on MI355X at n = 1000: 2 x 2 waves with six digits,
+// 2 x 4 waves (twice the rotated indices per genotype block) with four
+template <int ND>
+using DefaultRotI8L =
+    typename std::conditional<ND == kZSlices, RotI8L<2, 2, 4, 1, ND>, RotI8L<2, 4, 4, 1, ND>>::type;
 
 template <class R>
 __global__ __launch_bounds__(R::NT) void rotate_u8_i8_lds_kernel(const uint8_t *__restrict__ X, int64_t rows, int n,
@@ -467,7 +475,9 @@ __global__ __launch_bounds__(R::NT) void rotate_u8_i8_lds_kernel(const uint8_t *
 #pragma unroll
     for (int y = 0; y < FN; ++y) {
         const int k = k_base + wn * FN * 16 + y * 16 + l16;
-        const double off = zs.off[k], sc = zs.scale[k];
+        // ND leading digits: the offset of their sum, and 2^-E_k times 256^(kZSlices - ND)
+        const double off = zs.off[(ND == kZSlices ? 0 : n_pad) + k];
+        const double sc = zs.scale[k] * (double)(1ull << (8 * (kZSlices - ND)));
 #pragma unroll
         for (int x = 0; x < FM; ++x)
 #pragma unroll
@@ -484,6 +494,7 @@ __global__ __launch_bounds__(R::NT) void rotate_u8_i8_lds_kernel(const uint8_t *
 }  // namespace
 
 void slice_z_int8(const double *zh, int n_pad, int8_t *q, double *off, double *scale) {
+    static_assert(kZSlicesShort >= 1 && kZSlicesShort <= kZSlices, "digit counts");
     // byte of digit d, row k, sample r in fragment order (see ZSlices)
     auto at = [&](int d, int k, int r) -> int8_t & {
         const int64_t blk = ((int64_t)d * (n_pad / 16) + k / 16) * (n_pad / 64) + r / 64;
@@ -497,19 +508,27 @@ void slice_z_int8(const double *zh, int n_pad, int8_t *q, double *off, double *s
         frexp(mx, &e);                            // mx < 2^e
         const int E = 8 * kZSlices - 2 - e;       // |z| 2^E < 2^(8 kZSlices - 2)
         scale[k] = mx > 0.0 ? ldexp(1.0, -E) : 0.0;
-        __int128 sum = 0;
+        __int128 sum = 0, sum_short = 0;
         for (int r = 0; r < n_pad; ++r) {
             int64_t v = mx > 0.0 ? llround(ldexp(z[r], E)) : 0;
             sum += v;
+            int64_t dig[kZSlices];
             for (int d = kZSlices - 1; d >= 1; --d) {   // balanced base-256 digits, low first
                 int64_t t = v & 255;
                 if (t >= 128) t -= 256;
-                at(d, k, r) = (int8_t)t;
+                dig[d] = t;
                 v = (v - t) / 256;
             }
-            at(0, k, r) = (int8_t)v;                    // |v| <= 65
+            dig[0] = v;                                 // |v| <= 65
+            int64_t q_short = 0;                        // the leading kZSlicesShort digits
+            for (int d = 0; d < kZSlices; ++d) {
+                at(d, k, r) = (int8_t)dig[d];
+                if (d < kZSlicesShort) q_short = q_short * 256 + dig[d];
+            }
+            sum_short += q_short;
         }
         off[k] = 128.0 * (double)sum;
+        off[n_pad + k] = 128.0 * (double)sum_short;
     }
 }
 
@@ -598,11 +617,19 @@ hipError_t launch_rotate_u8_i8_lds_t(const uint8_t *X, int64_t rows, int n, int6
 
 hipError_t launch_rotate(const void *X, int dtype, int64_t rows, int n, int64_t ldx, const double *Zrows,
                          int n_pad, const RotOut &out, hipStream_t s, const ZSlices *zs) {
-    if (dtype == GWAS_DT_U8 && zs && zs->q && n_pad <= kZSliceMaxNpad && n_pad % DefaultRotI8L::TN == 0 &&
-        n % 4 == 0 && ldx % 4 == 0 && ((uintptr_t)X) % 4 == 0)
-        return launch_rotate_u8_i8_lds_t<DefaultRotI8L>((const uint8_t *)X, rows, n, ldx, *zs, n_pad, out, s);
-    if (dtype == GWAS_DT_U8 && zs && zs->q && n_pad <= kZSliceMaxNpad && n_pad % DefaultRotI8::TN == 0)
-        return launch_rotate_u8_i8_t<DefaultRotI8>((const uint8_t *)X, rows, n, ldx, *zs, n_pad, out, s);
+    // all digits when an FP64 store is written, the leading ones otherwise
+    const bool full = out.f64 != nullptr;
+    if (dtype == GWAS_DT_U8 && zs && zs->q && n_pad <= kZSliceMaxNpad && n_pad % DefaultRotI8L<kZSlices>::TN == 0 &&
+        n_pad % DefaultRotI8L<kZSlicesShort>::TN == 0 && n % 4 == 0 && ldx % 4 == 0 && ((uintptr_t)X) % 4 == 0)
+        return full ? launch_rotate_u8_i8_lds_t<DefaultRotI8L<kZSlices>>((const uint8_t *)X, rows, n, ldx, *zs,
+                                                                         n_pad, out, s)
+                    : launch_rotate_u8_i8_lds_t<DefaultRotI8L<kZSlicesShort>>((const uint8_t *)X, rows, n, ldx,
+                                                                              *zs, n_pad, out, s);
+    if (dtype == GWAS_DT_U8 && zs && zs->q && n_pad <= kZSliceMaxNpad && n_pad % DefaultRotI8<kZSlices>::TN == 0)
+        return full ? launch_rotate_u8_i8_t<DefaultRotI8<kZSlices>>((const uint8_t *)X, rows, n, ldx, *zs, n_pad,
+                                                                    out, s)
+                    : launch_rotate_u8_i8_t<DefaultRotI8<kZSlicesShort>>((const uint8_t *)X, rows, n, ldx, *zs,
+                                                                         n_pad, out, s);
     return launch_rotate_t<DefaultRot>(X, dtype, rows, n, ldx, Zrows, n_pad, out, s);
 }
 

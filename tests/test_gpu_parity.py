@@ -79,12 +79,16 @@ def test_rotate_dtypes_and_device_input(tiny, dtype, torch_cuda):
     c.close()
 
 
+@pytest.mark.parametrize("full", [True, False])
 @pytest.mark.parametrize("n,m,shift", [(1000, 300, 0), (333, 257, 0), (1000, 300, 1), (64, 17, 0)])
-def test_genotype_rotation_full_byte_range(n, m, shift, torch_cuda):
+def test_genotype_rotation_full_byte_range(n, m, shift, full, torch_cuda):
     """Genotype bytes over the whole range 0..255 (the int8 kernels offset them
     to v - 128 and sum exact int32 digit products): every rotated value against
     the FP64 product. n = 1000 takes the LDS-staged kernel; n = 333, and rows
-    starting at an odd device address (shift = 1), the register-staged one."""
+    starting at an odd device address (shift = 1), the register-staged one.
+    With an FP64 store (full) all six Z digits are used and the FP64 values are
+    checked to 1e-12 of the maximum; without one, the leading four, and the
+    FP32 values are checked to 1e-7 of the maximum (FP32 rounding is 6e-8)."""
     torch = torch_cuda
     phi, xl, _, _, _ = synth.small(n, 3, 1, 1, seed=n + shift)
     xr = np.random.default_rng(n + m).integers(0, 256, size=(m, n), dtype=np.uint8)
@@ -92,7 +96,7 @@ def test_genotype_rotation_full_byte_range(n, m, shift, torch_cuda):
     xr[1] = 0
     w, z = np.linalg.eigh(phi)
     from paper_1210_7683_amd import gwas
-    c = gwas.Cohort(z, w, xl, m, forms=("f64", "f32"))
+    c = gwas.Cohort(z, w, xl, m, forms=("f64", "f32") if full else ("f32",))
     buf = torch.zeros(m * n + shift, dtype=torch.uint8, device="cuda")
     dev = buf[shift:].view(m, n)
     dev.copy_(torch.from_numpy(xr))
@@ -100,11 +104,14 @@ def test_genotype_rotation_full_byte_range(n, m, shift, torch_cuda):
     c.rotate(0, dev)
     torch.cuda.synchronize()
     ref = xr.astype(np.float64) @ z
-    got = c.copy_rotated(0, m, "f64")
-    err = np.abs(got - ref).max() / np.abs(ref).max()
-    print("n=%d m=%d shift=%d: max |rotated - FP64 product| / max = %.2e" % (n, m, shift, err))
-    assert err <= 1e-12
-    assert np.array_equal(c.copy_rotated(0, m, "f32"), got.astype(np.float32))
+    if full:
+        got = c.copy_rotated(0, m, "f64")
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        assert np.array_equal(c.copy_rotated(0, m, "f32"), got.astype(np.float32))
+    else:
+        err = np.abs(c.copy_rotated(0, m, "f32").astype(np.float64) - ref).max() / np.abs(ref).max()
+    print("n=%d m=%d shift=%d full=%d: max |rotated - FP64 product| / max = %.2e" % (n, m, shift, full, err))
+    assert err <= (1e-12 if full else 1e-7)
     c.close()
 
 

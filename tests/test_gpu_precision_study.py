@@ -39,10 +39,17 @@ def test_precision_study_paper_m1e6():
     print("oracle: %d problems over %d traits in %.1f s" % (ii.size, uj.size, time.perf_counter() - t0),
           flush=True)
     ti, tj = torch.from_numpy(ii).cuda(), torch.from_numpy(jj).cuda()
-    with gwas.Cohort(z, ev, xl, w.m, forms=ALL_FORMS) as c:
-        c.rotate(0, torch.from_numpy(xr).cuda())
-        yd = torch.from_numpy(y).cuda()
-        for form in ALL_FORMS:
+    xd = torch.from_numpy(xr).cuda()
+    yd = torch.from_numpy(y).cuda()
+    rng = np.random.default_rng(5)
+    i1 = np.sort(rng.choice(w.m, size=10_000, replace=False))
+    ref1 = oracle.gls(phi, xl, xr[i1], y[:1], h2[:1], trait=np.zeros(i1.size, dtype=np.int64))
+    t1 = torch.from_numpy(i1).cuda()
+    # one cohort per form, as a run of one form holds it: the rotation then
+    # uses all six Z digits for the FP64 form and the leading four otherwise
+    for form in ALL_FORMS:
+        with gwas.Cohort(z, ev, xl, w.m, forms=(form,)) as c:
+            c.rotate(0, xd)
             b = c.solve(yd, h2, form=form)
             got = b[ti, tj].cpu().numpy()
             finite = bool(torch.isfinite(b).all())
@@ -57,12 +64,9 @@ def test_precision_study_paper_m1e6():
             print("PRECISION " + json.dumps(stats), flush=True)
             assert finite
             assert e.max() <= TOL[form], stats
-        # single-trait calls (the dot-product kernel in the FP64 and FP32 forms)
-        rng = np.random.default_rng(5)
-        i1 = np.sort(rng.choice(w.m, size=10_000, replace=False))
-        ref1 = oracle.gls(phi, xl, xr[i1], y[:1], h2[:1], trait=np.zeros(i1.size, dtype=np.int64))
-        t1 = torch.from_numpy(i1).cuda()
-        for form in ("f64", "f32"):
+            if form not in ("f64", "f32"):
+                continue
+            # single-trait calls (the dot-product kernel in the FP64 and FP32 forms)
             c.reset_stats()
             b = c.solve(yd[:1], h2[:1], form=form)
             assert c.stats()["dot_launches"] == 1
