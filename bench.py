@@ -458,6 +458,9 @@ def main():
             "solve_only_gls_per_s": problems / (fused_ms * 1e-3),
             "fused_tflops": achieved,
             "mfma_frac": achieved / PEAK_TFLOPS[form],
+            # the paper's convention, (5 + 2(p-1)) n flops per problem over the whole step
+            # (its 40-core node: about 25 GFLOP/s on this count)
+            "paper_convention_tflops": cm.flops_per_gls_paper(w.n, w.p) * problems / (ms * 1e-3) / 1e12,
             "non_spd": st["non_spd"],
             "finite": bool(torch.isfinite(b).all()),
         }
