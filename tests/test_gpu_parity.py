@@ -279,6 +279,64 @@ def test_errors_are_reported(torch_cuda):
     c.close()
 
 
+@pytest.mark.parametrize("form", FORMS)
+def test_degenerate_heritabilities_against_oracle(form, torch_cuda):
+    """h2 = 0 (M = I: ordinary least squares, also checked against numpy's
+    lstsq), h2 at the edges of [0, 1] and h2 = 1 (M = Phi, allowed as Phi is
+    SPD), against the oracle at the form's bound."""
+    phi, xl, xr, y, _ = synth.small(150, 4, 90, 6, seed=23)
+    h2 = np.array([0.0, 1e-9, 0.5, 1 - 1e-9, 1.0, 0.999])
+    ref = oracle.gls_grid(phi, xl, xr, y, h2)
+    c = cohort(phi, xl, xr, forms=(form,))
+    b = c.solve(y, h2, form=form).cpu().numpy()
+    c.close()
+    err = scaled_err(b, ref)
+    print("%s: scaled max per h2 %s" % (form, np.array2string(err.max(axis=0), precision=2)))
+    assert err.max() <= TOL[form]
+    if form == "f64":
+        for i in range(0, 90, 17):
+            x = np.column_stack([xl.T, xr[i].astype(np.float64)])
+            ols = np.linalg.lstsq(x, y[0], rcond=None)[0]
+            assert np.abs(b[i, 0] - ols).max() <= 1e-10 * np.abs(ols).max()
+
+
+@pytest.mark.parametrize("form", ["f64", "f32", "bf16x6"])
+def test_maximum_n_against_the_diagonal_closed_form(form, torch_cuda):
+    """n = 16384 (the largest the ABI accepts: 256 rotation stages, a 16384-long
+    fused K loop) with Z = I, i.e. Phi = diag(w): then M_j is diagonal and Eq. 1
+    is evaluated directly, b = (X^T D X)^-1 X^T D y with D = M_j^-1, in FP64."""
+    torch = torch_cuda
+    n, p, m, t = 16384, 4, 96, 8
+    rng = np.random.default_rng(16384)
+    w = rng.uniform(0.5, 2.0, n)
+    xl = np.vstack([np.ones(n), rng.standard_normal((p - 2, n))])
+    xr = rng.integers(0, 3, size=(m, n), dtype=np.uint8)
+    y = rng.standard_normal((t, n))
+    h2 = rng.uniform(0.1, 0.9, t)
+    xf = xr.astype(np.float64)
+    ref = np.empty((m, t, p))
+    for j in range(t):
+        d = 1.0 / (h2[j] * w + 1.0 - h2[j])
+        a = xl * d                                   # (p-1) x n
+        s = np.empty((m, p, p))
+        s[:, :p - 1, :p - 1] = a @ xl.T
+        s[:, :p - 1, p - 1] = (a @ xf.T).T
+        s[:, p - 1, :p - 1] = s[:, :p - 1, p - 1]
+        s[:, p - 1, p - 1] = (xf * xf) @ d
+        r = np.empty((m, p))
+        r[:, :p - 1] = a @ y[j]
+        r[:, p - 1] = xf @ (d * y[j])
+        ref[:, j] = np.linalg.solve(s, r[..., None])[..., 0]
+    from paper_1210_7683_amd import gwas
+    with gwas.Cohort(np.eye(n), w, xl, m, forms=(form,), max_traits=t) as c:
+        c.rotate(0, torch.from_numpy(xr).cuda())
+        b = c.solve(y, h2, form=form).cpu().numpy()
+    err = scaled_err(b, ref)
+    print("n=%d %s: scaled max %.2e" % (n, form, err.max()))
+    assert np.isfinite(b).all()
+    assert err.max() <= TOL[form]
+
+
 @pytest.fixture(scope="module")
 def paper_m1e5(torch_cuda):
     """The paper-shape workload (n = 1000, p = 4, m = 1e5, t = 1000) resident on the GPU."""
