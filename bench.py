@@ -11,7 +11,9 @@ eigendecomposition of the kinship matrix is setup and is not timed.
 
 The headline value is the FP32 form's throughput (GLS problems/s); the FP64
 and split-BF16 forms are timed the same way and reported beside it, each with
-its fused kernel's fraction of the MFMA peak of its own precision. The
+its fused kernel's fraction of the MFMA peak of its own precision. A short run
+of the serving workload (100 requests at 16/s on a resident m = 1e6 cohort)
+adds the p50/p99 request latency under "serving". The
 oracle (plain FP64 C, dense Cholesky per problem) is timed on the host cores
 on a bounded sample as a reference point.
 
@@ -276,27 +278,33 @@ def serve_bench(args):
     """Serving: resident cohort n = 1000, m = 1e6; Poisson arrivals; each request a
     trait block with t ~ log-uniform[1, 512], its own h2 and p - 1 ~ U{1..7}; b
     streamed to pinned host memory and checksummed; p50/p99 latency at a fixed rate."""
+    line = run_serving(args.workload, args.forms.split(",")[0], args.rate, args.requests, args.warmup_requests,
+                       args.slots, args.ring_slots, args.skip_checksum, args.grid_wgs)
+    print(json.dumps(line), flush=True)
+
+
+def run_serving(workload, form, rate, requests, warmup_requests, slots=8, ring_slots=0, skip_checksum=False,
+                grid_wgs=0):
     import torch
 
     import synth
     from paper_1210_7683_amd import gwas
 
-    w = synth.WORKLOADS[args.workload]
-    form = args.forms.split(",")[0]
+    w = synth.WORKLOADS[workload]
     t0 = time.perf_counter()
     phi, xl = synth.kinship(w), synth.covariates(w)       # intercept + 6 covariates: p up to 8
     xr = synth.snps(w)
     ev, z = np.linalg.eigh(phi)
-    reqs = synth.requests(w, args.warmup_requests + args.requests, args.rate)
-    log("inputs drawn in %.1f s; %d requests at %.1f/s" % (time.perf_counter() - t0, len(reqs), args.rate))
+    reqs = synth.requests(w, warmup_requests + requests, rate)
+    log("inputs drawn in %.1f s; %d requests at %.1f/s" % (time.perf_counter() - t0, len(reqs), rate))
     cohort = gwas.Cohort(z, ev, xl, w.m, forms=(form,))
     xr_d = torch.from_numpy(xr).cuda()
     cohort.rotate(0, xr_d)
     torch.cuda.synchronize()
     del xr_d
-    srv = gwas.Server(cohort, form=form, max_slots=args.slots, max_traits=512,
-                      host_threads=min(16, os.cpu_count() or 1), ring_slots=args.ring_slots,
-                      skip_checksum=args.skip_checksum, grid_wgs=args.grid_wgs)
+    srv = gwas.Server(cohort, form=form, max_slots=slots, max_traits=512,
+                      host_threads=min(16, os.cpu_count() or 1), ring_slots=ring_slots,
+                      skip_checksum=skip_checksum, grid_wgs=grid_wgs)
     start = gwas.clock() + 0.2
     tickets = []
     for r in reqs:
@@ -308,7 +316,7 @@ def serve_bench(args):
     sst = srv.stats()
     srv.close()
     cohort.close()
-    meas = list(range(args.warmup_requests, len(reqs)))
+    meas = list(range(warmup_requests, len(reqs)))
     lat = np.array([res[k]["t_done"] - (start + reqs[k].arrival_s) for k in meas])
     qwait = np.array([res[k]["t_admit"] - (start + reqs[k].arrival_s) for k in meas])
     problems = sum(res[k]["problems"] for k in meas)
@@ -320,18 +328,18 @@ def serve_bench(args):
     line = {
         "metric": "serving: p50/p99 latency and GLS problems/s at a fixed arrival rate",
         "value": problems / span, "unit": "GLS problems/s", "n_gpus": 1, "dtype": form,
-        "config": {"workload": w.name, "n": w.n, "m": w.m, "rate_hz": args.rate,
-                   "requests": len(meas), "warmup_requests": args.warmup_requests, "slots": args.slots,
+        "config": {"workload": w.name, "n": w.n, "m": w.m, "rate_hz": rate,
+                   "requests": len(meas), "warmup_requests": warmup_requests, "slots": slots,
                    "t": "log-uniform[1,512]", "p": "2..8", "form": form},
         "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
         "latency_max_s": float(lat.max()), "queue_wait_p99_s": float(np.percentile(qwait, 99)),
         "mean_traits": float(np.mean([reqs[k].y.shape[0] for k in meas])),
         "d2h_gbps": bytes_b / span / 1e9, "window_s": span, "all_done": ok,
-        "server": sst, "checksummed": not args.skip_checksum,
+        "server": sst, "checksummed": not skip_checksum,
     }
     log("serving at %.1f req/s: p50 %.3f s, p99 %.3f s, %.3e GLS/s, b to host %.1f GB/s" %
-        (args.rate, line["latency_p50_s"], line["latency_p99_s"], line["value"], line["d2h_gbps"]))
-    print(json.dumps(line), flush=True)
+        (rate, line["latency_p50_s"], line["latency_p99_s"], line["value"], line["d2h_gbps"]))
+    return line
 
 
 def main():
@@ -344,6 +352,10 @@ def main():
     ap.add_argument("--f32-flush", type=int, default=None,
                     help="FP32 form: FP64 fold interval in chunks of 16 samples (library default 2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="paper-shape bench: skip the short serving run that reports p50/p99 latency")
+    ap.add_argument("--serving-requests", type=int, default=100,
+                    help="paper-shape bench: measured requests of the short serving run")
     ap.add_argument("--rate", type=float, default=16.0, help="serving: request arrival rate (1/s)")
     ap.add_argument("--requests", type=int, default=200, help="serving: measured requests")
     ap.add_argument("--warmup-requests", type=int, default=20)
@@ -495,6 +507,15 @@ def main():
                      "flops_per_launch": mult * flops_gls * problems},
         "forms": results,
     }
+    if not args.no_serving:
+        # the metric's p99: a short run of the serving workload (the full one is
+        # --workload serve_m1e6), reported beside the grid's throughput
+        log("serving: %d requests at %.0f/s on the resident m = 1e6 cohort ..." % (args.serving_requests, args.rate))
+        s = run_serving("serve_m1e6", "f32", args.rate, args.serving_requests, 10)
+        line["serving"] = {"workload": "serve_m1e6", "form": "f32", "rate_hz": args.rate,
+                           "requests": s["config"]["requests"], "latency_p50_s": s["latency_p50_s"],
+                           "latency_p99_s": s["latency_p99_s"], "gls_per_s": s["value"],
+                           "d2h_gbps": s["d2h_gbps"], "all_done": s["all_done"]}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         line["cpu_baseline"] = cpu_baseline(w, phi, xl)
