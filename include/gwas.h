@@ -149,9 +149,11 @@ gwas_status gwas_setup(gwas_ctx **ctx, int32_t n, int32_t p, const double *Z, co
  * (Algorithm 5, preloop); the result is kept in every resident form (FP64;
  * rounded to FP32; split to BF16 hi/lo and hi/mid/lo). FP64 and FP32 X_R: an
  * FP64 MFMA GEMM. Genotype bytes (GWAS_DT_U8): int8 MFMAs against Z in
- * fixed point (47 bits per eigenvector, relative to its largest entry)
- * sliced into six int8 digits, with exact integer sums recombined in FP64;
- * the result differs from the FP64 GEMM by about 1e-14 relative.
+ * fixed point sliced into int8 digits, with exact integer sums recombined in
+ * FP64: six digits (47 bits per eigenvector, relative to its largest entry;
+ * about 3e-14 of the row's maximum from the FP64 GEMM) when the context keeps
+ * the FP64 form, else the leading four (about 4e-8 of the row's maximum, at
+ * the FP32 rounding of the stored values).
  *   X_R        n x mb, SNP-major, element type dtype (GWAS_DT_*)
  *   on_device  nonzero: X_R is device memory; zero: host memory (copied in
  *              bounded chunks through a device staging buffer)
