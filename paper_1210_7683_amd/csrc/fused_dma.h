@@ -1,5 +1,5 @@
 // The fused contraction + solve of fused.h with the operands staged by direct
-// global->LDS loads (global_load_lds_dwordx4), for all three forms.
+// global->LDS loads (global_load_lds_dwordx4), for all four forms.
 //
 // LDS layout: the staging buffer is a sequence of 1 KB blocks, each holding one
 // MFMA operand fragment in lane order: lane l of a wave owns bytes
@@ -12,16 +12,20 @@
 // them as the k = l / 16 element of 2 (FP64), 4 (FP32) or 1 (BF16, k-block of
 // 8) MFMAs, the same way for both operands, so every product pairs equal k.
 //
-// One stage holds KB groups of every operand row (KB * 64 bytes per row). The
-// loop per stage: wait for the stage's loads, barrier, read the fragments of
-// the whole stage into registers, barrier, issue the next stage's loads into
-// the same LDS (they run under this stage's MFMAs), compute.
+// One stage holds KB groups of every operand row (KB * 64 bytes per row). With
+// one LDS buffer the loop per stage is: wait for the stage's loads, barrier,
+// read the fragments of the whole stage into registers, barrier, issue the
+// next stage's loads into the same LDS (they run under this stage's MFMAs),
+// compute. With two (PIPE): wait, barrier, issue the next stage's loads into
+// the other buffer, read this stage's fragments (inline-assembly reads, see
+// lds_dma.h), compute.
 //
-// Split BF16: only x' hi and lo are staged; the split of x'^2 is formed from
-// them in registers (square_split), which halves the SNP-side bytes.
-// FP32 with FLUSH: one stage is one 32-sample window (KB = 2); the window's
-// FP32 accumulators are added to FP64 sums after its last MFMA and the next
-// window's first MFMA starts from zero.
+// Split BF16: only the pieces of x' are staged (hi, lo; or hi, mid, lo); the
+// split of x'^2 is formed from them in registers (square_split,
+// square_split3), which halves the SNP-side bytes.
+// FP32 and three-piece BF16 with FLUSH: one stage is one 32-sample window (KB =
+// 2 and 1); the window's FP32 accumulators are added to FP64 sums after its
+// last MFMA and the next window's first MFMA starts from zero.
 #pragma once
 
 #include "fused.h"
