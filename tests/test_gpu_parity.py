@@ -276,6 +276,10 @@ def test_errors_are_reported(torch_cuda):
     with pytest.raises(gwas.GwasError):
         c.rotate(8, xr[:5])
     assert c.solve(y, h2, form="f32", m=0).shape == (0, 3, 4)
+    c.rotate(3, xr[:0])                                     # an empty SNP block is a no-op
+    with pytest.raises(gwas.GwasError) as e:
+        c.solve(y[:0], h2[:0], form="f32")                  # tb = 0
+    assert e.value.status == gwas.EINVAL
     c.close()
 
 
