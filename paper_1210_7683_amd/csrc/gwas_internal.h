@@ -120,8 +120,8 @@ struct ZSlices {
 void slice_z_int8(const double *zh, int n_pad, int8_t *q, double *off, double *scale);
 
 // out[row0 + i][k] = sum_r X[i][r] Z[k][r]  for i < rows, k < n_pad. Genotype
-// bytes (GWAS_DT_U8) with zs given and n_pad <= kZSliceMaxNpad use the int8
-// digit kernel; every other case FP64 MFMA.
+// bytes (GWAS_DT_U8) use the int8 digit kernels and need zs (n_pad <=
+// kZSliceMaxNpad; hipErrorInvalidValue otherwise); FP64 and FP32 inputs FP64 MFMA.
 hipError_t launch_rotate(const void *X, int dtype, int64_t rows, int n, int64_t ldx,
                          const double *Zrows, int n_pad, const RotOut &out, hipStream_t s,
                          const ZSlices *zs = nullptr);

@@ -3,7 +3,7 @@
 // As a GEMM, out[i][k] = sum_r X[i][r] Z[k][r] (rows of Z are eigenvectors):
 // both operands are contiguous along the samples r. FP64 and FP32 inputs are
 // computed in FP64 MFMA (v_mfma_f64_16x16x4f64) over LDS-staged K chunks;
-// genotype bytes on the int8 MFMAs against Z sliced into int8 digits, whose
+// genotype bytes only on the int8 MFMAs against Z sliced into int8 digits, whose
 // sums are exact integers (the slicing of a floating-point operand into
 // integer digits with exact integer products and sums follows Ozaki's scheme
 // for emulating high-precision GEMM on integer matrix units).
@@ -36,6 +36,7 @@ struct RotTile {
     static constexpr int LDS = (TM + TN) * LD * 8;
 };
 
+// fastest of a tile sweep on MI355X (n = 1000)
 using DefaultRot = RotTile<128, 64, 32, 4, 1>;
 // few rows (a trait block): 4x the workgroups; 1000 x 1000 on MI355X 0.059 ms
 // against 0.14 ms with the default tile
@@ -60,7 +61,7 @@ __device__ __forceinline__ void rot_store(const RotOut &out, int64_t i, int k, d
         out.bf3[ps + o] = md;
         out.bf3[2 * ps + o] = l;
     }
-}   // fastest of a tile sweep on MI355X (n = 1000)
+}
 
 template <typename Tin, class R>
 __global__ __launch_bounds__(R::NT) void rotate_kernel(const Tin *__restrict__ X, int64_t rows, int n,
@@ -100,26 +101,11 @@ __global__ __launch_bounds__(R::NT) void rotate_kernel(const Tin *__restrict__ X
         for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
     double va[R::EA], vb[R::EB];
-    // genotype rows are often only 8-byte aligned (n = 1000): uint8 input is
-    // read 8 samples per load when the whole group is in range and aligned
-    const bool vec8 = sizeof(Tin) == 1 && (R::EA % 8) == 0 && (ldx % 8) == 0 && (((uintptr_t)X) % 8) == 0;
     auto gload = [&](int k0) {
-        if (vec8 && gi < rows && k0 + acol + R::EA <= n) {
 #pragma unroll
-            for (int e = 0; e < R::EA; e += 8) {
-                const uint2 v = *(const uint2 *)((const uint8_t *)xrow + k0 + acol + e);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    va[e + q] = (double)((v.x >> (8 * q)) & 0xffu);
-                    va[e + 4 + q] = (double)((v.y >> (8 * q)) & 0xffu);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int e = 0; e < R::EA; ++e) {
-                const int r = k0 + acol + e;
-                va[e] = (gi < rows && r < n) ? (double)xrow[r] : 0.0;
-            }
+        for (int e = 0; e < R::EA; ++e) {
+            const int r = k0 + acol + e;
+            va[e] = (gi < rows && r < n) ? (double)xrow[r] : 0.0;
         }
 #pragma unroll
         for (int e = 0; e < R::EB; e += 2) {
@@ -550,9 +536,6 @@ hipError_t launch_rotate_t(const void *X, int dtype, int64_t rows, int n, int64_
             if (e == hipSuccess)
                 e = hipFuncSetAttribute((const void *)rotate_kernel<float, R>,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, R::LDS);
-            if (e == hipSuccess)
-                e = hipFuncSetAttribute((const void *)rotate_kernel<uint8_t, R>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, R::LDS);
             if (e != hipSuccess) return e;
             attr_set = true;
         }
@@ -566,11 +549,7 @@ hipError_t launch_rotate_t(const void *X, int dtype, int64_t rows, int n, int64_
         hipLaunchKernelGGL((rotate_kernel<float, R>), grid, block, R::LDS, s, (const float *)X, rows, n, ldx,
                            Zrows, n_pad, out);
         break;
-    case GWAS_DT_U8:
-        hipLaunchKernelGGL((rotate_kernel<uint8_t, R>), grid, block, R::LDS, s, (const uint8_t *)X, rows, n, ldx,
-                           Zrows, n_pad, out);
-        break;
-    default:
+    default:   // genotype bytes go to the int8 digit kernels only
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -633,6 +612,7 @@ hipError_t launch_rotate(const void *X, int dtype, int64_t rows, int n, int64_t 
                                                                     out, s)
                     : launch_rotate_u8_i8_t<DefaultRotI8<kZSlicesShort>>((const uint8_t *)X, rows, n, ldx, *zs,
                                                                          n_pad, out, s);
+    if (dtype == GWAS_DT_U8) return hipErrorInvalidValue;   // needs the digits of Z
     const int64_t wgs = ((rows + DefaultRot::TM - 1) / DefaultRot::TM) * (n_pad / DefaultRot::TN);
     if (wgs < 1024 && n_pad % SmallRot::TN == 0)   // fewer than 4 workgroups per CU
         return launch_rotate_t<SmallRot>(X, dtype, rows, n, ldx, Zrows, n_pad, out, s);
