@@ -73,9 +73,11 @@ typedef struct gwas_options {
     int32_t device;      /* HIP device ordinal; -1: the current device                 */
     int32_t max_traits;  /* traits handled per internal trait sub-block; 0: 1024       */
     int32_t slab_snps;   /* SNPs per D2H slab when b goes to the host; 0: 16384        */
-    int32_t f32_flush;   /* FP32 form: 2 folds the FP32 accumulators into FP64 sums
-                            after every 32 samples (default), 0 never; other values
-                            are rejected with GWAS_EINVAL                           */
+    int32_t f32_flush;   /* FP32 form: 2 (default) adds the FP32 accumulators to FP64
+                            sums: for b_B (the sum X_R^T D y, which cancels) four
+                            chains of 8 samples each per 32 samples, for the others
+                            every 64 samples; 0 never; other values are rejected
+                            with GWAS_EINVAL                                       */
     int32_t timing;      /* nonzero: time every fused and rotation launch with HIP
                             events on its stream (read back by gwas_stats)           */
     int32_t ring_slots;  /* gwas_solve_stream: pinned host slots of the b ring; 0: 4  */

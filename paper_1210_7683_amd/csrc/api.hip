@@ -153,7 +153,7 @@ gwas_status gwas_setup(gwas_ctx **out, int32_t n, int32_t p, const double *Z, co
         opt->host_threads < 0 || opt->ring_slots > 64 || opt->host_threads > 256)
         return fail(GWAS_EINVAL, "negative option");
     if (opt->f32_flush != 0 && opt->f32_flush != 2)
-        return fail(GWAS_EINVAL, "f32_flush = %d: 0 (no fold) or 2 (fold every 32 samples)", opt->f32_flush);
+        return fail(GWAS_EINVAL, "f32_flush = %d: 0 (no fold) or 2 (FP64 folds, the default)", opt->f32_flush);
     const uint32_t forms = opt->forms ? opt->forms : 7u;
     if (forms & ~15u) return fail(GWAS_EINVAL, "unknown form bits 0x%x", forms);
     if (!all_finite(Z, (size_t)n * n) || !all_finite(w, n) || !all_finite(X_L, (size_t)n * (p - 1)))

@@ -15,7 +15,8 @@
 //
 // Forms (template FORM):
 //   F64:    double operands, v_mfma_f64_16x16x4f64
-//   F32:    float operands,  v_mfma_f32_16x16x4f32 (optional FP64 folding)
+//   F32:    float operands,  v_mfma_f32_16x16x4f32, FP32 accumulation added to
+//           FP64 sums (b_B in chains of 8 samples, the others every 64)
 //   BF16X3: bf16 hi/lo operands, v_mfma_f32_16x16x32_bf16, three products
 //           hi*hi + hi*lo + lo*hi per pair, FP32 accumulation
 //   BF16X6: bf16 hi/mid/lo operands, six products (all but mid*lo, lo*mid,

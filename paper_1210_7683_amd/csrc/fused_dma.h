@@ -23,9 +23,14 @@
 // Split BF16: only the pieces of x' are staged (hi, lo; or hi, mid, lo); the
 // split of x'^2 is formed from them in registers (square_split,
 // square_split3), which halves the SNP-side bytes.
-// FP32 and three-piece BF16 with FLUSH: one stage is one 32-sample window (KB =
-// 2 and 1); the window's FP32 accumulators are added to FP64 sums after its
-// last MFMA and the next window's first MFMA starts from zero.
+// FP64 folds (FLUSH): FP32 accumulators are added to FP64 sums at the end of
+// each window and the next window's first MFMA starts from zero. FP32 form
+// (KB = 2, 8 MFMAs of 4 samples per sum and stage): b_B, the sum that cancels,
+// in four chains per stage, one per MFMA slot e of the two 16-sample groups, so
+// each chain adds 8 products in 2 MFMAs (the rounding of 8-sample windows),
+// all four folded at the stage end; the other p sums in windows of
+// kF32LongWindow stages. Three-piece BF16 (KB = 1): every sum in windows of
+// one stage (32 samples).
 #pragma once
 
 #include "fused.h"
@@ -89,6 +94,9 @@ template <> struct DmaFrag<GWAS_FORM_BF16X6> { using type = bf16x8; using acc = 
 // 1 KB aligned) as its staging memory. Every thread of the workgroup calls it
 // with the same arguments (it contains workgroup barriers); on return all of
 // its global->LDS loads have completed and its LDS is no longer read.
+// FP32 form: stages (32 samples each) per FP64 fold window of the sums other than b_B
+constexpr int kF32LongWindow = 2;
+
 template <int FORM, int P, bool FLUSH, class T>
 __device__ __forceinline__ void dma_tile(const FusedArgs &a, int64_t tile, uint8_t *lds) {
     using C = DmaCfg<FORM, P, T>;
@@ -167,6 +175,9 @@ __device__ __forceinline__ void dma_tile(const FusedArgs &a, int64_t tile, uint8
 
     acc_t acc[NQ][FM][FN];
     d4 acc64[FLUSH ? NQ : 1][FLUSH ? FM : 1][FLUSH ? FN : 1];
+    // FP32 with FLUSH: b_B in four chains (MFMA slot e), restarted every stage
+    constexpr bool SPLIT_BB = FLUSH && FORM == GWAS_FORM_F32;
+    acc_t accb[SPLIT_BB ? FM : 1][SPLIT_BB ? FN : 1][4];
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
@@ -175,6 +186,8 @@ __device__ __forceinline__ void dma_tile(const FusedArgs &a, int64_t tile, uint8
             for (int y = 0; y < FN; ++y) {
                 acc[q][x][y] = acc_t{0, 0, 0, 0};
                 if constexpr (FLUSH) acc64[q][x][y] = d4{0, 0, 0, 0};
+                if constexpr (SPLIT_BB)
+                    for (int e = 0; e < 4; ++e) accb[x][y][e] = acc_t{0, 0, 0, 0};
             }
 
     issue(0);
@@ -221,9 +234,11 @@ __device__ __forceinline__ void dma_tile(const FusedArgs &a, int64_t tile, uint8
             if (c + 1 < nstages) issue(c + 1);    // the next stage's loads run under the MFMAs
         }
 
+        // stages per window of the sums folded at stage ends
+        constexpr int WS = FORM == GWAS_FORM_F32 ? kF32LongWindow : 1;
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
-            const bool fresh = FLUSH && kb == 0;   // an FP32 window starts at zero
+            const bool fresh = FLUSH && kb == 0 && c % WS == 0;   // an FP32 window starts at zero
 #pragma unroll
             for (int x = 0; x < FM; ++x) {
                 if constexpr (FORM == GWAS_FORM_F64) {
@@ -250,6 +265,14 @@ __device__ __forceinline__ void dma_tile(const FusedArgs &a, int64_t tile, uint8
 #pragma unroll
                             for (int e = 0; e < 4; ++e) {
                                 const float av = q == 0 ? xs[e] * xs[e] : xs[e];
+                                if constexpr (SPLIT_BB) {
+                                    if (q == NQ - 1) {   // b_B: chain e, restarted at the stage's first group
+                                        acc_t &v = accb[x][y][e];
+                                        v = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bs[e], kb == 0 ? acc_t{0, 0, 0, 0} : v,
+                                                                                 0, 0, 0);
+                                        continue;
+                                    }
+                                }
                                 acc[q][x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(
                                     av, bs[e], (fresh && e == 0) ? acc_t{0, 0, 0, 0} : acc[q][x][y], 0, 0, 0);
                             }
@@ -294,15 +317,27 @@ __device__ __forceinline__ void dma_tile(const FusedArgs &a, int64_t tile, uint8
                 }
             }
         }
+        if constexpr (SPLIT_BB) {   // b_B's four chains of this stage
+#pragma unroll
+            for (int x = 0; x < FM; ++x)
+#pragma unroll
+                for (int y = 0; y < FN; ++y)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        acc64[NQ - 1][x][y][r] += ((double)accb[x][y][0][r] + (double)accb[x][y][1][r]) +
+                                                  ((double)accb[x][y][2][r] + (double)accb[x][y][3][r]);
+        }
         if constexpr (FLUSH) {
+            if (c % WS == WS - 1 || c == nstages - 1) {   // the window ends with this stage
 #pragma unroll
-            for (int q = 0; q < NQ; ++q)
+                for (int q = 0; q < (SPLIT_BB ? NQ - 1 : NQ); ++q)   // FP32 b_B: folded above
 #pragma unroll
-                for (int x = 0; x < FM; ++x)
+                    for (int x = 0; x < FM; ++x)
 #pragma unroll
-                    for (int y = 0; y < FN; ++y)
+                        for (int y = 0; y < FN; ++y)
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) acc64[q][x][y][r] += (double)acc[q][x][y][r];
+                            for (int r = 0; r < 4; ++r) acc64[q][x][y][r] += (double)acc[q][x][y][r];
+            }
         }
     }
 
