@@ -175,9 +175,9 @@ __device__ __forceinline__ void dma_tile(const FusedArgs &a, int64_t tile, uint8
 
     acc_t acc[NQ][FM][FN];
     d4 acc64[FLUSH ? NQ : 1][FLUSH ? FM : 1][FLUSH ? FN : 1];
-    // FP32 with FLUSH: b_B in four chains (MFMA slot e), restarted every stage
+    // FP32 with FLUSH: b_B in four chains per stage (MFMA slot e), each run
+    // and folded on its own after the stage's other MFMAs
     constexpr bool SPLIT_BB = FLUSH && FORM == GWAS_FORM_F32;
-    acc_t accb[SPLIT_BB ? FM : 1][SPLIT_BB ? FN : 1][4];
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
@@ -186,8 +186,6 @@ __device__ __forceinline__ void dma_tile(const FusedArgs &a, int64_t tile, uint8
             for (int y = 0; y < FN; ++y) {
                 acc[q][x][y] = acc_t{0, 0, 0, 0};
                 if constexpr (FLUSH) acc64[q][x][y] = d4{0, 0, 0, 0};
-                if constexpr (SPLIT_BB)
-                    for (int e = 0; e < 4; ++e) accb[x][y][e] = acc_t{0, 0, 0, 0};
             }
 
     issue(0);
@@ -266,12 +264,7 @@ __device__ __forceinline__ void dma_tile(const FusedArgs &a, int64_t tile, uint8
                             for (int e = 0; e < 4; ++e) {
                                 const float av = q == 0 ? xs[e] * xs[e] : xs[e];
                                 if constexpr (SPLIT_BB) {
-                                    if (q == NQ - 1) {   // b_B: chain e, restarted at the stage's first group
-                                        acc_t &v = accb[x][y][e];
-                                        v = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bs[e], kb == 0 ? acc_t{0, 0, 0, 0} : v,
-                                                                                 0, 0, 0);
-                                        continue;
-                                    }
+                                    if (q == NQ - 1) continue;   // b_B: after the kb loop
                                 }
                                 acc[q][x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(
                                     av, bs[e], (fresh && e == 0) ? acc_t{0, 0, 0, 0} : acc[q][x][y], 0, 0, 0);
@@ -317,15 +310,27 @@ __device__ __forceinline__ void dma_tile(const FusedArgs &a, int64_t tile, uint8
                 }
             }
         }
-        if constexpr (SPLIT_BB) {   // b_B's four chains of this stage
+        if constexpr (SPLIT_BB) {
+            // b_B: chain e = the MFMAs of slot e of both 16-sample groups (8
+            // products), folded at once, so one chain is live at a time
+            static_assert(KB == 2, "two groups per stage");
 #pragma unroll
-            for (int x = 0; x < FM; ++x)
+            for (int x = 0; x < FM; ++x) {
+                const float4 x0 = xa[0][0][x], x1 = xa[1][0][x];
+                const float a0[4] = {x0.x, x0.y, x0.z, x0.w}, a1[4] = {x1.x, x1.y, x1.z, x1.w};
 #pragma unroll
-                for (int y = 0; y < FN; ++y)
+                for (int y = 0; y < FN; ++y) {
+                    const float4 y0 = yb[0][NQ - 1][y], y1 = yb[1][NQ - 1][y];
+                    const float b0[4] = {y0.x, y0.y, y0.z, y0.w}, b1[4] = {y1.x, y1.y, y1.z, y1.w};
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        acc64[NQ - 1][x][y][r] += ((double)accb[x][y][0][r] + (double)accb[x][y][1][r]) +
-                                                  ((double)accb[x][y][2][r] + (double)accb[x][y][3][r]);
+                    for (int e = 0; e < 4; ++e) {
+                        acc_t v = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[e], b0[e], acc_t{0, 0, 0, 0}, 0, 0, 0);
+                        v = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[e], b1[e], v, 0, 0, 0);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc64[NQ - 1][x][y][r] += (double)v[r];
+                    }
+                }
+            }
         }
         if constexpr (FLUSH) {
             if (c % WS == WS - 1 || c == nstages - 1) {   // the window ends with this stage
