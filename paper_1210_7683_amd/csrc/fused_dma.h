@@ -27,8 +27,9 @@
 // each window and the next window's first MFMA starts from zero. FP32 form
 // (KB = 2, 8 MFMAs of 4 samples per sum and stage): b_B, the sum that cancels,
 // in four chains per stage, one per MFMA slot e of the two 16-sample groups, so
-// each chain adds 8 products in 2 MFMAs (the rounding of 8-sample windows),
-// all four folded at the stage end; the other p sums in windows of
+// each chain adds 8 products in 2 MFMAs (the rounding of 8-sample windows); the
+// chains run one after another after the stage's other MFMAs, each folded as
+// it ends, so one chain is live at a time; the other p sums in windows of
 // kF32LongWindow stages. Three-piece BF16 (KB = 1): every sum in windows of
 // one stage (32 samples).
 #pragma once
