@@ -351,7 +351,7 @@ def main():
     ap.add_argument("--workload", default="paper_m1e5")
     ap.add_argument("--forms", default=DEFAULT_FORMS, help="headline form first")
     ap.add_argument("--f32-flush", type=int, default=None,
-                    help="FP32 form: FP64 fold interval in chunks of 16 samples (library default 2)")
+                    help="FP32 form: 2 = FP64 folds (the library default), 0 = FP32 accumulation only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true",
                     help="paper-shape bench: skip the short serving run that reports p50/p99 latency")

@@ -55,7 +55,8 @@ typedef int32_t gwas_status;
 /* precision forms of the O(m t p n) contractions (the Gram assembly and the
  * p x p solve are FP64 in every form) */
 #define GWAS_FORM_F64 0    /* FP64 operands, FP64 MFMA accumulation; b in FP64          */
-#define GWAS_FORM_F32 1    /* FP32 operands, FP32 MFMA accumulation; b in FP32          */
+#define GWAS_FORM_F32 1    /* FP32 operands, FP32 MFMA accumulation added to FP64 sums
+                              (gwas_options.f32_flush); b in FP32                       */
 #define GWAS_FORM_BF16X3 2 /* split BF16 operands x = hi + lo, hi*hi + hi*lo + lo*hi,
                               FP32 MFMA accumulation; b in FP32                          */
 #define GWAS_FORM_BF16X6 3 /* split BF16 in three pieces x = hi + mid + lo (the FP32 value

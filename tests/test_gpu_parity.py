@@ -424,9 +424,9 @@ def test_streamed_slabs_match_resident_b_and_checksums(form, torch_cuda):
 
 
 def test_large_n_sampled_against_oracle(torch_cuda):
-    """n = 4096 samples (a K loop four times the paper's, 128 FP64-fold windows in
-    the FP32 form), m = 1500, t = 8, every form; 300 sampled problems against the
-    oracle (one dense Cholesky of each M_j)."""
+    """n = 4096 samples (a K loop four times the paper's, 128 stages of FP64 folds
+    in the FP32 form), m = 1500, t = 8, every form; 300 sampled problems against
+    the oracle (one dense Cholesky of each M_j)."""
     torch = torch_cuda
     n, p, m, t = 4096, 4, 1500, 8
     phi, xl, xr, y, h2 = synth.small(n, p, m, t, seed=4096, k=2 * n)
