@@ -166,6 +166,29 @@ def test_ragged_shapes_and_p(form, n, p, m, t, torch_cuda):
     assert np.quantile(err, 0.99) <= TOL[form]
 
 
+def test_fp32_without_fp64_folds(torch_cuda):
+    """f32_flush = 0: the FP32 form accumulates the whole K loop in FP32 (no FP64
+    folds). No bound is stated for this variant; it is checked against ten times
+    the FP32 bound, against the default (folded) result, which must differ from it
+    and be at least as accurate over the grid, at a ragged n over several stages
+    and trait tiles."""
+    phi, xl, xr, y, h2 = synth.small(333, 4, 300, 40, seed=3301)
+    ref = oracle.gls_grid(phi, xl, xr, y, h2)
+    c0 = cohort(phi, xl, xr, forms=("f32",), f32_flush=0)
+    b0 = c0.solve(y, h2, form="f32").cpu().numpy()
+    c0.close()
+    c2 = cohort(phi, xl, xr, forms=("f32",))
+    b2 = c2.solve(y, h2, form="f32").cpu().numpy()
+    c2.close()
+    e0, e2 = scaled_err(b0, ref), scaled_err(b2, ref)
+    print("n=333 f32 without folds: scaled max %.3e median %.3e; with folds: max %.3e median %.3e" % (
+        e0.max(), np.median(e0), e2.max(), np.median(e2)))
+    assert e0.max() <= 10 * TOL["f32"]
+    assert e2.max() <= TOL["f32"]
+    assert not np.array_equal(b0, b2)
+    assert np.median(e2) <= np.median(e0)
+
+
 @pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("n,p,m,t", [(200, 2, 333, 1), (77, 4, 100, 2), (130, 9, 129, 3),
                                      (1000, 4, 70, 1), (1000, 4, 70, 4), (64, 20, 40, 1),
