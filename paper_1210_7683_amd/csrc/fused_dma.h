@@ -90,14 +90,14 @@ template <> struct DmaFrag<GWAS_FORM_F32> { using type = float4; using acc = f4;
 template <> struct DmaFrag<GWAS_FORM_BF16X3> { using type = bf16x8; using acc = f4; };
 template <> struct DmaFrag<GWAS_FORM_BF16X6> { using type = bf16x8; using acc = f4; };
 
+// FP32 form: stages (32 samples each) per FP64 fold window of the sums other than b_B
+constexpr int kF32LongWindow = 2;
+
 // One TM x TN tile of problems (tile index over the tiles of a, traits fastest),
 // computed by a whole workgroup of C::NT threads with `lds` (C::LDS bytes,
 // 1 KB aligned) as its staging memory. Every thread of the workgroup calls it
 // with the same arguments (it contains workgroup barriers); on return all of
 // its global->LDS loads have completed and its LDS is no longer read.
-// FP32 form: stages (32 samples each) per FP64 fold window of the sums other than b_B
-constexpr int kF32LongWindow = 2;
-
 template <int FORM, int P, bool FLUSH, class T>
 __device__ __forceinline__ void dma_tile(const FusedArgs &a, int64_t tile, uint8_t *lds) {
     using C = DmaCfg<FORM, P, T>;
