@@ -308,11 +308,13 @@ def run_serving(workload, form, rate, requests, warmup_requests, slots=8, ring_s
                       skip_checksum=skip_checksum, grid_wgs=grid_wgs)
     start = gwas.clock() + 0.2
     tickets = []
-    for r in reqs:
+    for i, r in enumerate(reqs):
         delay = start + r.arrival_s - gwas.clock()
         if delay > 0:
             time.sleep(delay)
         tickets.append(srv.submit(r.y, r.h2, r.p))
+        if (i + 1) % 500 == 0:
+            log("serving: %d of %d requests submitted" % (i + 1, len(reqs)))
     res = [srv.wait(tk, timeout=600) for tk in tickets]
     sst = srv.stats()
     srv.close()
