@@ -12,7 +12,7 @@ eigendecomposition of the kinship matrix is setup and is not timed.
 The headline value is the FP32 form's throughput (GLS problems/s); the FP64
 and split-BF16 forms are timed the same way and reported beside it, each with
 its fused kernel's fraction of the MFMA peak of its own precision. A short run
-of the serving workload (100 requests at 16/s on a resident m = 1e6 cohort)
+of the serving workload (500 requests at 16/s on a resident m = 1e6 cohort)
 adds the p50/p99 request latency under "serving". The
 oracle (plain FP64 C, dense Cholesky per problem) is timed on the host cores
 on a bounded sample as a reference point.
@@ -357,7 +357,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true",
                     help="paper-shape bench: skip the short serving run that reports p50/p99 latency")
-    ap.add_argument("--serving-requests", type=int, default=100,
+    ap.add_argument("--serving-requests", type=int, default=500,
                     help="paper-shape bench: measured requests of the short serving run")
     ap.add_argument("--rate", type=float, default=16.0, help="serving: request arrival rate (1/s)")
     ap.add_argument("--requests", type=int, default=200, help="serving: measured requests")
@@ -514,7 +514,7 @@ def main():
         # the metric's p99: a short run of the serving workload (the full one is
         # --workload serve_m1e6), reported beside the grid's throughput
         log("serving: %d requests at %.0f/s on the resident m = 1e6 cohort ..." % (args.serving_requests, args.rate))
-        s = run_serving("serve_m1e6", "f32", args.rate, args.serving_requests, 10)
+        s = run_serving("serve_m1e6", "f32", args.rate, args.serving_requests, 20)
         line["serving"] = {"workload": "serve_m1e6", "form": "f32", "rate_hz": args.rate,
                            "requests": s["config"]["requests"], "latency_p50_s": s["latency_p50_s"],
                            "latency_p99_s": s["latency_p99_s"], "gls_per_s": s["value"],
