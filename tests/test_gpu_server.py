@@ -3,7 +3,8 @@
 Requests carry their own traits, heritabilities and covariate count p (a
 prefix of the cohort's intercept-first covariates). Each result is checked
 against the FP64 oracle, and a request's b is required to be bitwise the same
-when it runs alone and when it runs in a mix with other requests.
+when it runs alone and when it runs in a mix with other requests, and, with the
+cohort's full covariate set, as the direct solve of the same traits.
 """
 import numpy as np
 import pytest
@@ -71,6 +72,23 @@ def test_alone_equals_mix_and_matches_oracle(cohort_f32, form):
         ref = oracle.gls_grid(d["phi"], d["xl"][: p - 1], d["xr"], y, h2)
         err = scaled_err(b, ref)
         assert err.max() <= TOL[form], (p, y.shape[0], err.max())
+
+
+@pytest.mark.parametrize("form", ["f32", "bf16x3"])
+def test_served_b_equals_the_direct_solve(cohort_f32, form):
+    """A request with the cohort's full covariate set gets, bitwise, the b that
+    gwas_solve computes for the same traits (the same per-problem tile
+    arithmetic: K order, MFMA products and FP64 folds), alone and in a mix."""
+    from paper_1210_7683_amd import gwas
+    d = cohort_f32
+    rng = np.random.default_rng(77)
+    reqs = [(rng.standard_normal((t, N)), rng.uniform(0.1, 0.9, t), PMAX) for t in (5, 17, 40)]
+    with gwas.Server(d["c"], form=form, max_slots=3, item_problems=6000, max_traits=64) as srv:
+        served, _ = _run(srv, reqs, together=True)
+    for (y, h2, _), b in zip(reqs, served):
+        direct = d["c"].solve(y, h2, form=form).cpu().numpy()
+        diff = np.abs(direct.astype(np.float64) - b).max()
+        assert np.array_equal(direct, b), (form, y.shape[0], diff)
 
 
 def test_ring_checksums(cohort_f32):
