@@ -280,6 +280,24 @@ def test_rank_deficient_snps_give_nan_and_are_counted(form, torch_cuda):
     c.close()
 
 
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("t", [1, 6])
+def test_dependent_covariates_give_nan_for_every_problem(form, t, torch_cuda):
+    """Covariates that are linearly dependent make S_TL_j singular for every
+    trait (X_i never has full rank): every b is NaN and counted, as in the
+    oracle; t = 1 takes the dot-product kernel in the FP64 and FP32 forms."""
+    phi, xl, xr, y, h2 = synth.small(96, 4, 37, t, seed=17)
+    xl = xl.copy()
+    xl[2] = 3.0 * xl[1]
+    ref = oracle.gls_grid(phi, xl, xr, y, h2)
+    assert np.isnan(ref).all()
+    c = cohort(phi, xl, xr, forms=(form,))
+    b = c.solve(y, h2, form=form).cpu().numpy()
+    assert np.isnan(b).all()
+    assert c.stats()["non_spd"] == 37 * t
+    c.close()
+
+
 def test_errors_are_reported(torch_cuda):
     from paper_1210_7683_amd import gwas
     phi, xl, xr, y, h2 = synth.small(64, 4, 10, 3, seed=1)

@@ -188,6 +188,17 @@ def test_rank_deficient_snp_gives_nan_and_is_counted(oracle_lib, small):
     assert np.isfinite(b[:2]).all() and np.isnan(b[2:]).all()
 
 
+def test_dependent_covariates_give_nan_for_every_problem(oracle_lib, small):
+    """Two covariates that are multiples of each other leave no X_i of full rank
+    (Section 2 assumes full rank): every b is NaN and every problem counted."""
+    phi, xl, xr, y, h2 = small
+    xl = np.vstack([xl, 3.0 * xl[-1]])
+    b, bad = oracle_lib.gls(phi, xl, xr[:5], np.repeat(y[:1], 5, 0), np.repeat(h2[:1], 5),
+                            return_non_spd=True)
+    assert bad == 5
+    assert np.isnan(b).all()
+
+
 def test_non_spd_covariance_is_an_error(oracle_lib):
     n = 8
     v = np.ones(n)
