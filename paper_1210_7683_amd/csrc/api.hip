@@ -13,6 +13,15 @@
 
 using namespace gw;
 
+
+// the tile orders of the fused and rotation kernels cover every tile once, on
+// shapes that take each branch (whole and partial groups of 8 rows, tails of
+// 1 to 7 column tiles, multiples of 8, fewer than 8)
+static_assert(gw::tile_order_is_bijection<13, 63>() && gw::tile_order_is_bijection<16, 9>() &&
+                  gw::tile_order_is_bijection<7, 20>() && gw::tile_order_is_bijection<9, 8>() &&
+                  gw::tile_order_is_bijection<3, 5>() && gw::tile_order_is_bijection<24, 15>() &&
+                  gw::tile_order_is_bijection<98, 63>() && gw::tile_order_is_bijection<1, 17>(),
+              "tile_order must be a bijection");
 namespace gw {
 std::string &last_error() {
     thread_local std::string e;

@@ -360,7 +360,7 @@ __device__ __forceinline__ void dma_tile(const FusedArgs &a, int64_t tile, uint8
 // xcd_order, XCD x takes a contiguous eighth of the trait tiles and walks every
 // SNP tile, so its trait panels stay in its L2 while the SNP rows stream.
 // tile_order applies it to the largest multiple of 8 trait tiles and runs the
-// rest (fewer than 8 per SNP tile) after them.
+// rest (fewer than 8 per SNP tile) after them, all of a SNP tile's on one XCD.
 template <int FORM, int P, bool FLUSH, class T>
 __global__ __launch_bounds__((DmaCfg<FORM, P, T>::NT)) void fused_dma_kernel(FusedArgs a) {
     using C = DmaCfg<FORM, P, T>;

@@ -32,7 +32,7 @@ __device__ __forceinline__ int mfma16_row(int g, int r) { return F64 ? g + 4 * r
 
 // Workgroup -> tile order over ntn column tiles (see fused_dma.h): XCD-aware when
 // ntn is a multiple of 8, identity otherwise; a bijection of [0, tiles).
-__device__ __forceinline__ int64_t xcd_order(int64_t b, int ntn) {
+__host__ __device__ constexpr int64_t xcd_order(int64_t b, int ntn) {
     if (ntn % 8) return b;
     const int64_t x = b % 8, local = b / 8;
     const int g = ntn / 8;
@@ -40,10 +40,14 @@ __device__ __forceinline__ int64_t xcd_order(int64_t b, int ntn) {
 }
 
 // Workgroup -> tile (tm * ntn + tn) over ntm x ntn tiles, a bijection for any
-// ntn: the first 8 floor(ntn / 8) column tiles of every row in XCD-aware order
-// (each XCD a contiguous eighth of them), the remaining ntn mod 8 after them in
-// plain order; fewer than 8 column tiles: plain order.
-__device__ __forceinline__ int64_t tile_order(int64_t b, int64_t ntm, int ntn) {
+// ntn (checked at compile time in api.hip); workgroup b runs on XCD b mod 8.
+// The first 8 floor(ntn / 8) column tiles of every row come first, in
+// XCD-aware order (each XCD a contiguous eighth of them, over all rows). The
+// remaining r = ntn mod 8 column tiles follow by groups of 8 rows, XCD x taking
+// the r tiles of row 8 G + x, so that a row's tail tiles share one XCD's L2;
+// rows past the last whole group of 8, and grids with fewer than 8 column
+// tiles, run in plain order.
+__host__ __device__ constexpr int64_t tile_order(int64_t b, int64_t ntm, int ntn) {
     const int g = ntn / 8;
     if (g == 0) return b;
     const int n8 = 8 * g;
@@ -52,9 +56,27 @@ __device__ __forceinline__ int64_t tile_order(int64_t b, int64_t ntm, int ntn) {
         const int64_t t = xcd_order(b, n8);
         return (t / n8) * ntn + t % n8;
     }
-    const int r = ntn - n8;
-    b -= na;
-    return (b / r) * ntn + n8 + b % r;
+    const int r = ntn - n8;                      // > 0 here: b < ntm ntn
+    b -= na;                                     // na is a multiple of 8: b keeps its XCD
+    const int64_t nfull = (ntm / 8) * 8 * r;     // tail tiles of the whole groups of 8 rows
+    if (b < nfull) {
+        const int64_t k = b / 8, x = b % 8;
+        return ((k / r) * 8 + x) * ntn + n8 + k % r;
+    }
+    b -= nfull;
+    return ((ntm / 8) * 8 + b / r) * ntn + n8 + b % r;
+}
+
+// True if tile_order maps [0, NTM NTN) onto itself one to one.
+template <int64_t NTM, int NTN>
+constexpr bool tile_order_is_bijection() {
+    bool seen[NTM * NTN] = {};
+    for (int64_t b = 0; b < NTM * NTN; ++b) {
+        const int64_t t = tile_order(b, NTM, NTN);
+        if (t < 0 || t >= NTM * NTN || seen[t]) return false;
+        seen[t] = true;
+    }
+    return true;
 }
 
 // Round-to-nearest-even of an FP32 value to BF16 (finite inputs), as raw bits.
