@@ -81,12 +81,16 @@ def test_rotate_dtypes_and_device_input(tiny, dtype, torch_cuda):
 
 
 @pytest.mark.parametrize("full", [True, False])
-@pytest.mark.parametrize("n,m,shift", [(1000, 300, 0), (333, 257, 0), (1000, 300, 1), (64, 17, 0)])
+@pytest.mark.parametrize("n,m,shift", [(1000, 300, 0), (333, 257, 0), (1000, 300, 1), (64, 17, 0),
+                                       (600, 1100, 0), (600, 1100, 1)])
 def test_genotype_rotation_full_byte_range(n, m, shift, full, torch_cuda):
     """Genotype bytes over the whole range 0..255 (the int8 kernels offset them
     to v - 128 and sum exact int32 digit products): every rotated value against
     the FP64 product. n = 1000 takes the LDS-staged kernel; n = 333, and rows
     starting at an odd device address (shift = 1), the register-staged one.
+    n = 600, m = 1100: 10 or 20 column tiles and 9 row tiles, so the tile order's
+    tail (column tiles past the last multiple of 8, by groups of 8 row tiles)
+    and its partial group are taken.
     With an FP64 store (full) all six Z digits are used and the FP64 values are
     checked to 1e-12 of the maximum; without one, the leading four, and the
     FP32 values are checked to 1e-7 of the maximum (FP32 rounding is 6e-8)."""
@@ -151,7 +155,8 @@ def test_genotype_rotation_ragged_n_and_rows(n, m, torch_cuda):
 
 @pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("n,p,m,t", [(200, 2, 333, 37), (77, 3, 100, 5), (130, 5, 129, 17),
-                                     (96, 8, 70, 33), (64, 13, 40, 9), (150, 20, 35, 18)])
+                                     (96, 8, 70, 33), (64, 13, 40, 9), (150, 20, 35, 18),
+                                     (128, 4, 1100, 150)])
 def test_ragged_shapes_and_p(form, n, p, m, t, torch_cuda):
     phi, xl, xr, y, h2 = synth.small(n, p, m, t, seed=n * 31 + p)
     ref = oracle.gls_grid(phi, xl, xr, y, h2)
