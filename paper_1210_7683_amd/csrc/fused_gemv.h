@@ -5,17 +5,18 @@
 // products that read each rotated SNP row once for all t traits: about
 // 2 (p+1) t flops per SNP-row element loaded, so the work is bound by HBM
 // bandwidth, not by the MFMAs (a 16-trait MFMA tile would compute 16 / t times
-// the useful work). Here each wave takes 16 SNP rows; lane (r, g) = (l mod 16,
-// l / 16) multiplies row r's samples 32 w + 16 h + 4 g + {0..3} (h = 0, 1) of
-// each 32-sample window w with the trait panels (read through the cache, the
-// same 16 bytes for the 16 lanes of a group), so one load instruction covers
-// 64 contiguous bytes of each of 16 rows. The four lane groups' partial sums
-// are added with two cross-lane exchanges; lane group g then solves trait g.
+// the useful work). Each wave takes 4 SNP rows at a time; lane (k, rr) =
+// (l mod 16, l / 16) multiplies row rr's samples 128 w + 64 h + 4 k + {0..3}
+// (h = 0, 1) of each 128-sample window w with the trait panels, which the
+// workgroup copies into LDS once, so one load instruction reads 256 contiguous
+// bytes (FP32; 512 FP64) of each of 4 rows, whole cache lines. The 16 lanes'
+// partial sums of a row are added with four cross-lane exchanges; lane k then
+// solves trait k.
 //
 // Arithmetic: FP64 form in FP64. FP32 and split-BF16 forms multiply and add in
-// FP32 within each 32-sample window (8 products per lane) and add the window
-// sums in FP64; the split-BF16 operands are used as hi + lo (exact in FP32),
-// which keeps the lo*lo product the three-product MFMA form drops.
+// FP32 within each window (8 products per lane) and add the window sums in
+// FP64; the split-BF16 operands are used as hi + lo (exact in FP32), which
+// keeps the lo*lo product the three-product MFMA form drops.
 #pragma once
 
 #include <algorithm>
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(256) void fused_gemv_kernel(FusedArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t gemv_lds_raw[];
     ct *pan = (ct *)gemv_lds_raw;   // [q][j][n_pad], in the compute type
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r = lane & 15, g = lane >> 4;
+    const int k = lane & 15, rr = lane >> 4;   // lane k of row rr: 4 rows per wave
     const int n_pad = a.n_pad;
     const int esz = FORM == GWAS_FORM_F64 ? 8 : (FORM == GWAS_FORM_F32 ? 4 : 2);
     const int64_t x_plane = a.a_plane_rows * n_pad;   // BF16 lo plane offset (elements)
@@ -83,9 +84,9 @@ __global__ __launch_bounds__(256) void fused_gemv_kernel(FusedArgs a) {
     }
     __syncthreads();
 
-    const int64_t nblk = (a.mi + 63) / 64;
+    const int64_t nblk = (a.mi + 15) / 16;
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-        const int64_t i = (blk * 4 + wave) * 16 + r;
+        const int64_t i = (blk * 4 + wave) * 4 + rr;
         const int64_t ic = i < a.mi ? i : a.mi - 1;   // rows past the range load a valid row, store nothing
         const uint8_t *xrow = (const uint8_t *)a.a + (a.i0 + ic) * n_pad * esz;
 
@@ -95,11 +96,21 @@ __global__ __launch_bounds__(256) void fused_gemv_kernel(FusedArgs a) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) acc[j][q] = 0.0;
 
+        // lane k takes samples s0 .. s0 + 3 and s0 + 64 .. s0 + 67 of each
+        // 128-sample window (s0 = 128 w + 4 k): the 16 lanes of a row read 256
+        // contiguous bytes (FP32) per load. n_pad is a multiple of 64, so the
+        // second half of the last window is absent for the whole wave or for none.
 #pragma unroll 2
-        for (int s0 = 4 * g; s0 < n_pad; s0 += 32) {
+        for (int s0 = 4 * k; s0 < n_pad; s0 += 128) {
+            const bool two = s0 + 64 < n_pad;
             ct x[8];
             gemv_load4<FORM>(xrow, x_plane, s0, x);
-            gemv_load4<FORM>(xrow, x_plane, s0 + 16, x + 4);
+            if (two) {
+                gemv_load4<FORM>(xrow, x_plane, s0 + 64, x + 4);
+            } else {
+#pragma unroll
+                for (int e = 4; e < 8; ++e) x[e] = 0;
+            }
             ct xx[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) xx[e] = x[e] * x[e];
@@ -110,9 +121,9 @@ __global__ __launch_bounds__(256) void fused_gemv_kernel(FusedArgs a) {
                     const ct *pp = pan + (q * T + j) * n_pad + s0;
                     ct pv[8];
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        pv[k] = pp[k];
-                        pv[4 + k] = pp[16 + k];
+                    for (int e = 0; e < 4; ++e) {
+                        pv[e] = pp[e];
+                        pv[4 + e] = two ? pp[64 + e] : ct(0);
                     }
                     ct w = 0;
 #pragma unroll
@@ -120,18 +131,20 @@ __global__ __launch_bounds__(256) void fused_gemv_kernel(FusedArgs a) {
                     acc[j][q] += (double)w;
                 }
         }
-        // sum the four lane groups of each row
+        // sum the 16 lanes of each row
 #pragma unroll
         for (int j = 0; j < T; ++j)
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 double v = acc[j][q];
-                v += __shfl_xor(v, 16);
-                v += __shfl_xor(v, 32);
+                v += __shfl_xor(v, 1);
+                v += __shfl_xor(v, 2);
+                v += __shfl_xor(v, 4);
+                v += __shfl_xor(v, 8);
                 acc[j][q] = v;
             }
-        // lane group g solves trait g of row i
-        const int j = g;
+        // lane k solves trait k of row i
+        const int j = k;
         if (i < a.mi && j < T) {
             double cq[NQ];
 #pragma unroll
@@ -157,8 +170,8 @@ template <int FORM, int P>
 hipError_t launch_gemv_t(const FusedArgs &a, hipStream_t s) {
     if (a.mi <= 0 || a.tb <= 0) return hipSuccess;
     const int64_t lds = gemv_lds<FORM>(P, a.tb, a.n_pad);
-    if (a.tb > kSmallT || a.n_pad % 32 || lds > kGemvLdsMax) return hipErrorInvalidValue;
-    const int64_t nblk = (a.mi + 63) / 64;
+    if (a.tb > kSmallT || a.n_pad % 64 || lds > kGemvLdsMax) return hipErrorInvalidValue;
+    const int64_t nblk = (a.mi + 15) / 16;
     const dim3 grid((unsigned)std::min<int64_t>(nblk, 2048)), block(256);
     static_assert(kSmallT == 3, "one instantiation per trait count");
     switch (a.tb) {
