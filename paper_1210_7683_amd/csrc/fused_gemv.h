@@ -5,13 +5,14 @@
 // products that read each rotated SNP row once for all t traits: about
 // 2 (p+1) t flops per SNP-row element loaded, so the work is bound by HBM
 // bandwidth, not by the MFMAs (a 16-trait MFMA tile would compute 16 / t times
-// the useful work). Each wave takes 4 SNP rows at a time; lane (k, rr) =
-// (l mod 16, l / 16) multiplies row rr's samples 128 w + 64 h + 4 k + {0..3}
-// (h = 0, 1) of each 128-sample window w with the trait panels, which the
-// workgroup copies into LDS once, so one load instruction reads 256 contiguous
-// bytes (FP32; 512 FP64) of each of 4 rows, whole cache lines. The 16 lanes'
-// partial sums of a row are added with four cross-lane exchanges; lane k then
-// solves trait k.
+// the useful work). Each wave takes R SNP rows at a time with L = 64 / R lanes
+// per row (FP64: L = 16; FP32: L = 4); lane (k, rr) = (l mod L, l / L)
+// multiplies row rr's samples 8L w + 4L h + 4k + {0..3} (h = 0, 1) of each
+// 8L-sample window w with the trait panels, which the workgroup copies into LDS
+// once, so one load instruction reads 16L contiguous elements of each of R rows
+// (FP64: 512 bytes, whole cache lines; FP32: 64 bytes, with the panel reads of
+// a lane position shared by the R rows). The L lanes' partial sums of a row are
+// added with log2 L cross-lane exchanges; lane k then solves trait k.
 //
 // Arithmetic: FP64 form in FP64. FP32 and split-BF16 forms multiply and add in
 // FP32 within each window (8 products per lane) and add the window sums in
@@ -66,7 +67,10 @@ __global__ __launch_bounds__(256) void fused_gemv_kernel(FusedArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t gemv_lds_raw[];
     ct *pan = (ct *)gemv_lds_raw;   // [q][j][n_pad], in the compute type
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int k = lane & 15, rr = lane >> 4;   // lane k of row rr: 4 rows per wave
+    // L consecutive lanes per row, R rows per wave: 16 x 4 for FP64 (whole
+    // cache lines per row and load), 4 x 16 for FP32 (measured best at n = 1000)
+    constexpr int L = FORM == GWAS_FORM_F64 ? 16 : 4, R = 64 / L;
+    const int k = lane % L, rr = lane / L;   // lane k of row rr
     const int n_pad = a.n_pad;
     const int esz = FORM == GWAS_FORM_F64 ? 8 : (FORM == GWAS_FORM_F32 ? 4 : 2);
     const int64_t x_plane = a.a_plane_rows * n_pad;   // BF16 lo plane offset (elements)
@@ -84,9 +88,9 @@ __global__ __launch_bounds__(256) void fused_gemv_kernel(FusedArgs a) {
     }
     __syncthreads();
 
-    const int64_t nblk = (a.mi + 15) / 16;
+    const int64_t nblk = (a.mi + 4 * R - 1) / (4 * R);
     for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-        const int64_t i = (blk * 4 + wave) * 4 + rr;
+        const int64_t i = (blk * 4 + wave) * R + rr;
         const int64_t ic = i < a.mi ? i : a.mi - 1;   // rows past the range load a valid row, store nothing
         const uint8_t *xrow = (const uint8_t *)a.a + (a.i0 + ic) * n_pad * esz;
 
@@ -96,17 +100,18 @@ __global__ __launch_bounds__(256) void fused_gemv_kernel(FusedArgs a) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) acc[j][q] = 0.0;
 
-        // lane k takes samples s0 .. s0 + 3 and s0 + 64 .. s0 + 67 of each
-        // 128-sample window (s0 = 128 w + 4 k): the 16 lanes of a row read 256
-        // contiguous bytes (FP32) per load. n_pad is a multiple of 64, so the
-        // second half of the last window is absent for the whole wave or for none.
+        // lane k takes samples s0 .. s0 + 3 and s0 + 4L .. s0 + 4L + 3 of each
+        // 8L-sample window (s0 = 8L w + 4k): the L lanes of a row read 16L
+        // contiguous elements per load. n_pad is a multiple of 64, so the second
+        // half of the last window is absent for the whole wave or for none.
 #pragma unroll 2
-        for (int s0 = 4 * k; s0 < n_pad; s0 += 128) {
-            const bool two = s0 + 64 < n_pad;
+        for (int s0 = 4 * k; s0 < n_pad; s0 += 8 * L) {
+            // windows of 8L <= 64 samples always fit n_pad (a multiple of 64)
+            const bool two = 64 % (8 * L) == 0 || s0 + 4 * L < n_pad;
             ct x[8];
             gemv_load4<FORM>(xrow, x_plane, s0, x);
             if (two) {
-                gemv_load4<FORM>(xrow, x_plane, s0 + 64, x + 4);
+                gemv_load4<FORM>(xrow, x_plane, s0 + 4 * L, x + 4);
             } else {
 #pragma unroll
                 for (int e = 4; e < 8; ++e) x[e] = 0;
@@ -123,7 +128,7 @@ __global__ __launch_bounds__(256) void fused_gemv_kernel(FusedArgs a) {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         pv[e] = pp[e];
-                        pv[4 + e] = two ? pp[64 + e] : ct(0);
+                        pv[4 + e] = two ? pp[4 * L + e] : ct(0);
                     }
                     ct w = 0;
 #pragma unroll
@@ -131,16 +136,14 @@ __global__ __launch_bounds__(256) void fused_gemv_kernel(FusedArgs a) {
                     acc[j][q] += (double)w;
                 }
         }
-        // sum the 16 lanes of each row
+        // sum the L lanes of each row
 #pragma unroll
         for (int j = 0; j < T; ++j)
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 double v = acc[j][q];
-                v += __shfl_xor(v, 1);
-                v += __shfl_xor(v, 2);
-                v += __shfl_xor(v, 4);
-                v += __shfl_xor(v, 8);
+#pragma unroll
+                for (int o = 1; o < L; o <<= 1) v += __shfl_xor(v, o);
                 acc[j][q] = v;
             }
         // lane k solves trait k of row i
@@ -171,7 +174,8 @@ hipError_t launch_gemv_t(const FusedArgs &a, hipStream_t s) {
     if (a.mi <= 0 || a.tb <= 0) return hipSuccess;
     const int64_t lds = gemv_lds<FORM>(P, a.tb, a.n_pad);
     if (a.tb > kSmallT || a.n_pad % 64 || lds > kGemvLdsMax) return hipErrorInvalidValue;
-    const int64_t nblk = (a.mi + 15) / 16;
+    constexpr int RPW = 64 / (FORM == GWAS_FORM_F64 ? 16 : 4);   // rows per wave, as in the kernel
+    const int64_t nblk = (a.mi + 4 * RPW - 1) / (4 * RPW);
     const dim3 grid((unsigned)std::min<int64_t>(nblk, 2048)), block(256);
     static_assert(kSmallT == 3, "one instantiation per trait count");
     switch (a.tb) {
