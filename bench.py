@@ -372,7 +372,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the GLS grid shards along SNPs with no exchange, "
-              "and this build measures one GPU's share (use --gpus 1).", file=sys.stderr)
+              "and the bench measures one GPU's share (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
     import torch
