@@ -182,7 +182,8 @@ gwas_status gwas_rotate(gwas_ctx *ctx, int64_t m0, int64_t mb, const void *X_R, 
  *               copied out on a second stream while the next slab computes)
  * A problem whose Gram matrix S_ij is not numerically SPD (the SNP column is,
  * to the working precision, a combination of the covariates) gets b_ij = NaN
- * and is counted in gwas_stats_t.non_spd.
+ * and is counted in gwas_stats_t.non_spd; when the covariates themselves are
+ * dependent, so are all problems of every trait.
  * Errors: GWAS_EINVAL (range, tb, h2 out of range, form not resident),
  * GWAS_EHIP. The SNPs in range must have been rotated before.
  */
