@@ -8,8 +8,9 @@ solves Eq. (1) of the paper, b = (X^T M^{-1} X)^{-1} X^T M^{-1} y, with the
 covariance of Eq. (2), M = sigma2 (h2 Phi + (1 - h2) I), through a dense
 Cholesky factorisation of M (Section 3.1), in O(n^3) per trait.
 
-`rotated` (rotated.py) is a second, independent CPU reference: the paper's
-eigendecomposition-based reduction (Algorithms 1 and 5), in numpy FP64.
+`rotated` (rotated.py) is a second, independent CPU reference: Eq. (1) with
+M_j^{-1} = Z diag(d_j) Z^T from the eigendecomposition of Phi (Section 3.1),
+each problem's p x p normal equations formed in the rotated basis, in numpy FP64.
 """
 from __future__ import annotations
 

@@ -1,59 +1,45 @@
-"""Test infrastructure only: the paper's eigendecomposition-based reduction on the CPU.
+"""Test infrastructure only: Eq. (1) evaluated through the eigendecomposition of Phi.
 
-A second FP64 reference, independent of both the C oracle and the GPU path,
-written from Section 3 of the paper (Algorithms 1, 2 and 5):
+A second FP64 reference, independent of both the C oracle and the GPU path.
+It rests on one identity of Section 3.1: with Phi = Z diag(w) Z^T and
+Z orthogonal, M_j = h2_j Phi + (1 - h2_j) I = Z diag(h2_j w + 1 - h2_j) Z^T,
+so M_j^{-1} = Z diag(d_j) Z^T with d_j = 1 / (h2_j w + 1 - h2_j). Substituted
+into Eq. (1), every product X^T M_j^{-1} X' becomes (Z^T X)^T diag(d_j) (Z^T X'):
+the design matrix X_i = [X_L | x_i] and the trait y_j are rotated by Z^T once,
+and each problem is a weighted least-squares problem in the rotated basis,
 
-  Phi = Z Lambda Z^T;  X'_L = Z^T X_L;  X'_R = Z^T X_R;  Y' = Z^T Y;
-  per trait j:  D_j = sigma2_j (h2_j Lambda + (1 - h2_j) I),  K_j = D_j^{-1/2},
-                W_L = K_j X'_L,  v_j = K_j y'_j,  S_TL = W_L^T W_L,  b_T = W_L^T v_j;
-  per SNP i:    W_R = K_j x'_i,  S_BL = W_R^T W_L,  S_BR = W_R^T W_R,  b_B = W_R^T v_j,
-                b_ij = S_ij^{-1} [b_T; b_B],  S_ij = [[S_TL, S_BL^T], [S_BL, S_BR]].
+    G_ij = A_i^T diag(d_j) A_i,   r_ij = A_i^T diag(d_j) (Z^T y_j),   G_ij b_ij = r_ij,
 
-The paper writes K_j K_j^T = D_j^{-1/2} in its listings but defines
-K_j := D_j^{-1/2} in the text; the text's reading (K_j K_j^T = D_j^{-1}) is the
-one that reproduces Eq. (1), and is used here.
+with A_i = Z^T X_i (n x p). This module forms G_ij and r_ij whole for each
+problem and solves them with numpy's LU solve; it takes none of the paper's
+partitioning of G into covariate and SNP blocks and no square roots of d_j.
 """
 from __future__ import annotations
 
 import numpy as np
 
 
-def eig(phi):
-    """Phi = Z diag(lam) Z^T (Algorithm 5, first preloop step)."""
-    lam, z = np.linalg.eigh(np.asarray(phi, dtype=np.float64))
-    return z, lam
-
-
-def mt_gwas(xl, xr, y, h2, z, lam, sigma2=None):
-    """b [m][t][p] for X_L [(p-1)][n], X_R [m][n], Y [t][n], h2 [t], Phi = Z diag(lam) Z^T."""
+def gls_rotated(xl, xr, y, h2, z, w):
+    """b [m][t][p] for X_L [(p-1)][n], X_R [m][n], Y [t][n], h2 [t] and
+    Phi = Z diag(w) Z^T (Z orthogonal, eigenvectors in columns)."""
     xl = np.atleast_2d(np.asarray(xl, dtype=np.float64))
     xr = np.atleast_2d(np.asarray(xr, dtype=np.float64))
     y = np.atleast_2d(np.asarray(y, dtype=np.float64))
     h2 = np.atleast_1d(np.asarray(h2, dtype=np.float64))
-    sigma2 = np.ones_like(h2) if sigma2 is None else np.atleast_1d(np.asarray(sigma2, dtype=np.float64))
-    m, t, p = xr.shape[0], y.shape[0], xl.shape[0] + 1
-    xlp = z.T @ xl.T            # X'_L  n x (p-1)
-    xrp = z.T @ xr.T            # X'_R  n x m
-    yp = z.T @ y.T              # Y'    n x t
+    z = np.asarray(z, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    m, t, n = xr.shape[0], y.shape[0], z.shape[0]
+    p = xl.shape[0] + 1
+    # A_i = Z^T [X_L | x_i] for every SNP, stacked: a[i] is n x p
+    a = np.empty((m, n, p))
+    a[:, :, : p - 1] = (z.T @ xl.T)[None, :, :]
+    a[:, :, p - 1] = xr @ z
+    yr = y @ z                                  # row j = (Z^T y_j)^T
     b = np.empty((m, t, p))
     for j in range(t):
-        d = sigma2[j] * (h2[j] * lam + (1.0 - h2[j]))      # D_j
-        k = 1.0 / np.sqrt(d)                                # K_j = D_j^{-1/2}
-        wl = k[:, None] * xlp                               # W_L   n x (p-1)
-        v = k * yp[:, j]                                    # v_j
-        stl = wl.T @ wl                                     # S_TL
-        bt = wl.T @ v                                       # b_T
-        wr = k[:, None] * xrp                               # W_R for every SNP, n x m
-        sbl = wr.T @ wl                                     # S_BL  m x (p-1)
-        sbr = np.einsum("ki,ki->i", wr, wr)                 # S_BR  m
-        bb = wr.T @ v                                       # b_B   m
-        s = np.empty((m, p, p))
-        s[:, : p - 1, : p - 1] = stl
-        s[:, p - 1, : p - 1] = sbl
-        s[:, : p - 1, p - 1] = sbl
-        s[:, p - 1, p - 1] = sbr
-        rhs = np.empty((m, p))
-        rhs[:, : p - 1] = bt
-        rhs[:, p - 1] = bb
-        b[:, j, :] = np.linalg.solve(s, rhs[..., None])[..., 0]
+        d = 1.0 / (h2[j] * w + (1.0 - h2[j]))   # M_j^{-1} = Z diag(d) Z^T
+        da = a * d[None, :, None]               # diag(d) A_i
+        g = np.matmul(a.transpose(0, 2, 1), da)        # G_ij, m x p x p
+        r = np.matmul(da.transpose(0, 2, 1), yr[j])    # r_ij, m x p
+        b[:, j, :] = np.linalg.solve(g, r[..., None])[..., 0]
     return b

@@ -162,20 +162,20 @@ def test_agrees_with_rotated_reduction(oracle_lib):
     for n, m, t in [(128, 24, 5), (1000, 6, 2)]:
         phi, xl, xr, y, h2 = synth.small(n, 4, m, t, seed=n)
         b = oracle_lib.gls_grid(phi, xl, xr, y, h2)
-        z, lam = rot.eig(phi)
-        br = rot.mt_gwas(xl, xr, y, h2, z, lam)
+        lam, z = np.linalg.eigh(phi)
+        br = rot.gls_rotated(xl, xr, y, h2, z, lam)
         assert rel(br, b).max() < 1e-11
 
 
 def test_rotated_reduction_sign_and_order_invariance():
     import oracle.rotated as rot
     phi, xl, xr, y, h2 = synth.small(64, 4, 10, 3, seed=5)
-    z, lam = rot.eig(phi)
-    b = rot.mt_gwas(xl, xr, y, h2, z, lam)
+    lam, z = np.linalg.eigh(phi)
+    b = rot.gls_rotated(xl, xr, y, h2, z, lam)
     rng = np.random.default_rng(0)
     perm = rng.permutation(64)
     sign = rng.choice([-1.0, 1.0], size=64)
-    b2 = rot.mt_gwas(xl, xr, y, h2, (z * sign)[:, perm], lam[perm])
+    b2 = rot.gls_rotated(xl, xr, y, h2, (z * sign)[:, perm], lam[perm])
     assert rel(b2, b).max() < 1e-12
 
 
