@@ -314,8 +314,8 @@ typedef struct gwas_server gwas_server;
 typedef struct gwas_server_options {
     int64_t hbm_budget;  /* device bytes admitted requests may hold at once; 0: 8 GiB      */
     int32_t max_slots;   /* requests in flight at once, 1..32; 0: 8                        */
-    int32_t form;        /* GWAS_FORM_F64, _F32 or _BF16X3, used for every request (must be
-                            resident); GWAS_FORM_BF16X6 is not served: GWAS_EINVAL       */
+    int32_t form;        /* GWAS_FORM_F64, _F32, _BF16X3 or _BF16X6, used for every request
+                            (must be resident)                                            */
     int32_t item_problems; /* target problems (SNPs x traits) per work item; 0: 4194304    */
     int32_t max_traits;  /* largest request trait count accepted; 0: 1024                  */
     int32_t ring_slots;  /* pinned host ring slots; 0: 2 x max_slots                       */

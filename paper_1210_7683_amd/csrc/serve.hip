@@ -16,11 +16,13 @@ namespace {
 // Tile code of the direct solve (fused_dma.h) with one workgroup shape for all
 // p of a launch: 4 waves of one 16x16 block each, 64 SNPs x 16 traits per tile
 // (requests have few traits, so narrow trait tiles waste little).
+// The three-piece split BF16 form always folds its FP32 sums into FP64 per stage.
 template <int FORM, bool FLUSH>
 struct ServeTile {
     using type = typename std::conditional<FORM == GWAS_FORM_F64, DmaTile<4, 1, 1, 1, 1>,
                  typename std::conditional<FORM == GWAS_FORM_F32, DmaTile<4, 1, 1, 1, 2, true>,
                                            DmaTile<4, 1, 1, 1, 1, true>>::type>::type;
+    static_assert(FORM != GWAS_FORM_BF16X6 || FLUSH, "the three-piece form folds every stage");
 };
 
 template <int FORM, bool FLUSH>
@@ -104,6 +106,7 @@ void tile_shape_t(int p, int &tm, int &tn) {
 
 void serve_tile_shape(int form, bool flush, int p, int &tm, int &tn) {
     if (form == GWAS_FORM_F64) tile_shape_t<GWAS_FORM_F64, false>(p, tm, tn);
+    else if (form == GWAS_FORM_BF16X6) tile_shape_t<GWAS_FORM_BF16X6, true>(p, tm, tn);
     else if (form == GWAS_FORM_F32 && flush) tile_shape_t<GWAS_FORM_F32, true>(p, tm, tn);
     else if (form == GWAS_FORM_F32) tile_shape_t<GWAS_FORM_F32, false>(p, tm, tn);
     else tile_shape_t<GWAS_FORM_BF16X3, false>(p, tm, tn);
@@ -112,6 +115,7 @@ void serve_tile_shape(int form, bool flush, int p, int &tm, int &tn) {
 hipError_t launch_serve(int form, bool flush, const ServeBatch &bt, int grid, hipStream_t s) {
     if (grid <= 0 || bt.total_tiles <= 0) return hipSuccess;
     if (form == GWAS_FORM_F64) return launch_serve_t<GWAS_FORM_F64, false>(bt, grid, s);
+    if (form == GWAS_FORM_BF16X6) return launch_serve_t<GWAS_FORM_BF16X6, true>(bt, grid, s);
     if (form == GWAS_FORM_F32 && flush) return launch_serve_t<GWAS_FORM_F32, true>(bt, grid, s);
     if (form == GWAS_FORM_F32) return launch_serve_t<GWAS_FORM_F32, false>(bt, grid, s);
     return launch_serve_t<GWAS_FORM_BF16X3, false>(bt, grid, s);

@@ -106,7 +106,7 @@ struct Copy {
 
 size_t panel_bytes(int form, int p, int t, int n_pad) {
     const size_t elt = form == GWAS_FORM_F64 ? 8 : (form == GWAS_FORM_F32 ? 4 : 2);
-    const size_t planes = form == GWAS_FORM_BF16X3 ? 2 * (size_t)(p + 1) : (size_t)(p + 1);
+    const size_t planes = (form == GWAS_FORM_BF16X3 ? 2 : form == GWAS_FORM_BF16X6 ? 3 : 1) * (size_t)(p + 1);
     return elt * planes * t * n_pad;
 }
 
@@ -253,7 +253,8 @@ void sched_loop(gwas_server *s) {
     gwas_ctx *c = s->c;
     hipSetDevice(c->dev);
     const void *a_base = s->form == GWAS_FORM_F64 ? (const void *)c->xr64
-                       : s->form == GWAS_FORM_F32 ? (const void *)c->xr32 : (const void *)c->xrbf;
+                       : s->form == GWAS_FORM_F32 ? (const void *)c->xr32
+                       : s->form == GWAS_FORM_BF16X3 ? (const void *)c->xrbf : (const void *)c->xrbf3;
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         if (s->stop && s->queue.empty() && s->active.empty()) break;
@@ -547,9 +548,7 @@ gwas_status gwas_server_create(gwas_ctx *c, const gwas_server_options *opt, gwas
     if (!out) return fail(GWAS_EINVAL, "server pointer is NULL");
     *out = nullptr;
     if (!c || !opt) return fail(GWAS_EINVAL, "NULL argument");
-    if (opt->form == GWAS_FORM_BF16X6)
-        return fail(GWAS_EINVAL, "form %d is not served (FP64, FP32 and three-product split BF16 are)", opt->form);
-    if (opt->form < 0 || opt->form > 2 || !(c->forms & GWAS_FORM_BIT(opt->form)))
+    if (opt->form < 0 || opt->form > 3 || !(c->forms & GWAS_FORM_BIT(opt->form)))
         return fail(GWAS_EINVAL, "form %d is not resident", opt->form);
     if (opt->hbm_budget < 0 || opt->max_slots < 0 || opt->max_slots > kServeMaxItems || opt->item_problems < 0 ||
         opt->max_traits < 0 || opt->ring_slots < 0 || opt->host_threads < 0 || opt->ring_slots > 256 ||

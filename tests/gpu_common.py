@@ -44,8 +44,34 @@ def scaled_err(b_hat, b_ref, trait_axis=1):
     b_hat = np.asarray(b_hat, dtype=np.float64)
     b_ref = np.asarray(b_ref, dtype=np.float64)
     nb = np.linalg.norm(b_ref, axis=-1)
-    med = np.median(nb, axis=tuple(a for a in range(nb.ndim) if a != trait_axis), keepdims=True)
+    if trait_axis is None or nb.ndim < 2:   # one pooled median (a list of sampled problems)
+        med = np.median(nb)
+    else:
+        med = np.median(nb, axis=tuple(a for a in range(nb.ndim) if a != trait_axis), keepdims=True)
     return np.linalg.norm(b_hat - b_ref, axis=-1) / np.maximum(nb, med)
+
+
+def check_bound(b_hat, b_ref, form, bound=None, label=""):
+    """Assert a form's bound on b against a reference (problems along the last
+    axis but one, traits on axis 1 when b has three axes).
+
+    FP64: every problem's relative error ||b_hat - b|| / ||b|| is at most the
+    bound (1e-10 unless given). Reduced forms: the error scaled by
+    max(||b||, the trait's median ||b||) is at most the bound everywhere, and
+    the relative error at its 99th percentile; a pure-noise trait can have a
+    b close to zero, whose relative error is then the rounding floor of the
+    form's sums divided by ||b||. Returns (relative, scaled) errors."""
+    bound = TOL[form] if bound is None else bound
+    rel = rel_err(b_hat, b_ref)
+    sc = scaled_err(b_hat, b_ref)
+    print("%s%s: relative max %.3e median %.3e, scaled max %.3e (bound %.0e)" % (
+        label + " " if label else "", form, rel.max(), np.median(rel), sc.max(), bound))
+    if form == "f64":
+        assert rel.max() <= bound, (label, form, rel.max())
+    else:
+        assert sc.max() <= bound, (label, form, sc.max())
+        assert np.quantile(rel, 0.99) <= bound, (label, form, np.quantile(rel, 0.99))
+    return rel, sc
 
 
 def cohort(phi, xl, xr, forms=ALL_FORMS, m_capacity=None, **kw):

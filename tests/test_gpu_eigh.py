@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_common import TOL, scaled_err
+from tests.gpu_common import check_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -56,9 +56,7 @@ def test_solve_from_the_device_eigendecomposition_against_oracle(torch_cuda):
     c.rotate(0, xr)
     for form in ("f64", "f32", "bf16x6"):
         b = c.solve(y, h2, form=form).cpu().numpy()
-        err = scaled_err(b, ref).max()
-        print("%s: scaled max %.2e" % (form, err))
-        assert err <= TOL[form]
+        check_bound(b, ref, form, label="device eigendecomposition")
     c.close()
 
 

@@ -4,19 +4,21 @@ Every test here runs the kernels on cuda:0 and compares b element by element
 with the oracle (oracle/oracle.c, a dense-Cholesky solve of Eq. (1)) on the
 same seeded inputs, to the per-form bound: FP64 1e-10, FP32 and three-piece
 split BF16 1e-5, two-piece split BF16 1e-3 (its measured bound over whole
-paper-shape grids, with margin). On the paper-shaped workloads (p = 4)
-the bound applies to every problem's relative error ||b_hat - b|| / ||b||; on
-the ragged shapes (p from 2 to 20, short n) it applies to the error scaled by
-max(||b||, the trait's median ||b||), since with p = 2 a few problems out of
-thousands have ||b|| near zero and their relative error is the rounding floor
-of the sums divided by ||b|| (reported, not bounded).
+paper-shape grids, with margin). The FP64 form's bound applies to every
+problem's relative error ||b_hat - b|| / ||b|| in every test, and so do the
+reduced forms' bounds on the paper-shaped workloads (p = 4). On the ragged
+shapes (p from 2 to 20, short n) the reduced forms are bounded in the error
+scaled by max(||b||, the trait's median ||b||) and in the 99th percentile of
+the relative error, since with p = 2 a few problems out of thousands have
+||b|| near zero and their relative error is the rounding floor of the form's
+sums divided by ||b|| (reported, not bounded).
 """
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from tests.gpu_common import ALL_FORMS, TOL, cohort, grid_error_vs, rel_err, scaled_err
+from tests.gpu_common import ALL_FORMS, TOL, check_bound, cohort, grid_error_vs, rel_err, scaled_err
 
 pytestmark = pytest.mark.gpu
 
@@ -130,7 +132,7 @@ def test_full_byte_range_genotypes_solve_against_oracle(form, torch_cuda):
     c = cohort(phi, xl, xr, forms=(form,))
     b = c.solve(y, h2, form=form).cpu().numpy()
     c.close()
-    assert scaled_err(b, ref).max() <= TOL[form]
+    check_bound(b, ref, form, label="bytes 0..255")
 
 
 @pytest.mark.parametrize("n,m", [(77, 129), (200, 333), (1000, 300)])
@@ -163,12 +165,7 @@ def test_ragged_shapes_and_p(form, n, p, m, t, torch_cuda):
     c = cohort(phi, xl, xr, forms=(form,))
     b = c.solve(y, h2, form=form).cpu().numpy()
     c.close()
-    err = rel_err(b, ref)
-    sc = scaled_err(b, ref)
-    print("n=%d p=%d m=%d t=%d %s: relative max %.3e, scaled max %.3e" % (n, p, m, t, form,
-                                                                       err.max(), sc.max()))
-    assert sc.max() <= TOL[form]
-    assert np.quantile(err, 0.99) <= TOL[form]
+    check_bound(b, ref, form, label="n=%d p=%d m=%d t=%d" % (n, p, m, t))
 
 
 def test_fp32_without_fp64_folds(torch_cuda):
@@ -211,11 +208,7 @@ def test_small_trait_calls_use_the_dot_product_kernel(form, n, p, m, t, torch_cu
     n_pad = (n + 63) // 64 * 64
     dot = form in ("f64", "f32") and t <= 3 and (p + 1) * t * n_pad * (8 if form == "f64" else 4) <= 64 * 1024
     assert c.stats()["dot_launches"] == (1 if dot else 0)
-    err, sc = rel_err(b, ref), scaled_err(b, ref)
-    print("n=%d p=%d m=%d t=%d %s: relative max %.3e, scaled max %.3e" % (n, p, m, t, form,
-                                                                       err.max(), sc.max()))
-    assert sc.max() <= TOL[form]
-    assert np.quantile(err, 0.99) <= TOL[form]
+    check_bound(b, ref, form, label="n=%d p=%d m=%d t=%d" % (n, p, m, t))
     part = c.solve(y, h2, form=form, i0=3, m=m - 5).cpu().numpy()
     assert np.array_equal(part, b[3:m - 2])
     dt = torch.float64 if form == "f64" else torch.float32
@@ -233,7 +226,7 @@ def test_calls_with_four_traits_use_the_mfma_tiles(form, torch_cuda):
     c = cohort(phi, xl, xr, forms=(form,), max_traits=3)   # sub-blocks of 3 and 1 traits
     b = c.solve(y, h2, form=form).cpu().numpy()
     assert c.stats()["dot_launches"] == 0
-    assert scaled_err(b, ref).max() <= TOL[form]
+    check_bound(b, ref, form, label="t=4 in sub-blocks of 3")
     c.close()
 
 
@@ -281,8 +274,65 @@ def test_rank_deficient_snps_give_nan_and_are_counted(form, torch_cuda):
     assert np.isfinite(b[ok]).all()
     assert c.stats()["non_spd"] == 2 * 6
     ref = oracle.gls_grid(phi, xl, cols[ok], y, h2)
-    assert scaled_err(b[ok], ref).max() <= TOL[form]
+    check_bound(b[ok], ref, form, label="full-rank SNPs beside rank-deficient ones")
     c.close()
+
+
+def _schur_pivot_ratio(phi, xl, x, h2):
+    """s / S_BR of the SNP column x for each trait: the share of x's weighted
+    norm left once the covariates are projected out (FP64, from M_j^-1 = Z diag(d) Z^T)."""
+    w, z = np.linalg.eigh(phi)
+    a = z.T @ np.column_stack([xl.T, x])
+    out = []
+    for h in h2:
+        d = 1.0 / (h * w + 1.0 - h)
+        g = a.T @ (d[:, None] * a)
+        q = g.shape[0] - 1
+        u = np.linalg.solve(np.linalg.cholesky(g[:q, :q]), g[:q, q])
+        out.append((g[q, q] - u @ u) / g[q, q])
+    return np.array(out)
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_snps_between_the_rank_floors(form, torch_cuda):
+    """SNP columns close to the span of the covariates, x = X_L c + eps r, whose
+    Schur pivot ratio s / S_BR (about eps^2 |r|^2 / |x|^2) falls between the FP64
+    floor (1e-10) and the reduced forms' floors (1e-4 FP32 and three-piece split
+    BF16, 1e-3 two-piece). The FP64 form solves them and matches the oracle; the
+    reduced forms report NaN and count them, as their sums cannot resolve the
+    pivot. At ratio rho the pivot keeps about log10(1/rho) fewer digits, so two
+    correct FP64 evaluations differ by about 1e-15 / rho (measured between the
+    oracle and the CPU rotated reference: 3.6e-11 at rho = 3.5e-5, 2.6e-10 at
+    3.1e-6): the FP64 bound is 1e-10 at rho ~ 3e-5 and 1e-8 at rho ~ 3e-6."""
+    n, p, t = 128, 4, 6
+    phi, xl, xr, y, h2 = synth.small(n, p, 8, t, seed=77)
+    rng = np.random.default_rng(5)
+    base = rng.standard_normal(p - 1) @ xl
+    r = rng.standard_normal(n)
+    cols = xr.astype(np.float64)
+    band = {2: (1e-2, 1e-10), 5: (3e-3, 1e-8)}       # column -> (eps, FP64 bound)
+    for i, (eps, _) in band.items():
+        cols[i] = base + eps * r
+    ratio = {i: _schur_pivot_ratio(phi, xl, cols[i], h2) for i in band}
+    assert 2e-5 < ratio[2].min() and ratio[2].max() < 5e-5
+    assert 2e-6 < ratio[5].min() and ratio[5].max() < 5e-6
+    ref = oracle.gls_grid(phi, xl, cols, y, h2)
+    assert np.isfinite(ref).all()
+    c = cohort(phi, xl, cols, forms=(form,))
+    b = c.solve(y, h2, form=form).cpu().numpy()
+    non_spd = c.stats()["non_spd"]
+    c.close()
+    ok = np.setdiff1d(np.arange(8), list(band))
+    check_bound(b[ok], ref[ok], form, label="full-rank SNPs beside near-dependent ones")
+    if form == "f64":
+        assert non_spd == 0
+        for i, (eps, bound) in band.items():
+            e = rel_err(b[i], ref[i])
+            print("f64 pivot ratio %.1e: relative max %.3e (bound %.0e)" % (ratio[i].max(), e.max(), bound))
+            assert e.max() <= bound
+    else:
+        assert np.isnan(b[list(band)]).all()
+        assert non_spd == len(band) * t
 
 
 @pytest.mark.parametrize("form", FORMS)
@@ -302,10 +352,8 @@ def test_very_few_samples(form, n, p, torch_cuda):
         c = cohort(phi, xl, xr, forms=(form,))
         b = c.solve(y, h2, form=form).cpu().numpy()
         c.close()
-        sc = scaled_err(b, ref)
-        print("n=%d p=%d t=%d %s: scaled max %.3e (bound %.0e)" % (n, p, t, form, sc.max(), bound))
         assert np.isfinite(b).all()
-        assert sc.max() <= bound
+        check_bound(b, ref, form, bound=bound, label="n=%d p=%d t=%d" % (n, p, t))
 
 
 @pytest.mark.parametrize("form", FORMS)
@@ -364,9 +412,8 @@ def test_degenerate_heritabilities_against_oracle(form, torch_cuda):
     c = cohort(phi, xl, xr, forms=(form,))
     b = c.solve(y, h2, form=form).cpu().numpy()
     c.close()
-    err = scaled_err(b, ref)
-    print("%s: scaled max per h2 %s" % (form, np.array2string(err.max(axis=0), precision=2)))
-    assert err.max() <= TOL[form]
+    rel, sc = check_bound(b, ref, form, label="h2 at 0, 1 and their edges")
+    print("%s: relative max per h2 %s" % (form, np.array2string(rel.max(axis=0), precision=2)))
     if form == "f64":
         for i in range(0, 90, 17):
             x = np.column_stack([xl.T, xr[i].astype(np.float64)])
@@ -405,10 +452,8 @@ def test_maximum_n_against_the_diagonal_closed_form(form, torch_cuda):
     with gwas.Cohort(np.eye(n), w, xl, m, forms=(form,), max_traits=t) as c:
         c.rotate(0, torch.from_numpy(xr).cuda())
         b = c.solve(y, h2, form=form).cpu().numpy()
-    err = scaled_err(b, ref)
-    print("n=%d %s: scaled max %.2e" % (n, form, err.max()))
     assert np.isfinite(b).all()
-    assert err.max() <= TOL[form]
+    check_bound(b, ref, form, label="n=%d, Z = I" % n)
 
 
 @pytest.fixture(scope="module")

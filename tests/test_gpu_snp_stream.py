@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_common import ALL_FORMS, TOL, cohort, scaled_err
+from tests.gpu_common import ALL_FORMS, check_bound, cohort
 
 pytestmark = pytest.mark.gpu
 
@@ -61,7 +61,7 @@ def test_streamed_snps_equal_resident_solve(form, n, p, m, t, cap, slab, traits,
     b2, sums2 = collect(c, torch.from_numpy(xr).cuda(), y, h2, form)
     assert np.array_equal(b2, full) and sums2 == sums
     c.close()
-    assert scaled_err(b, oracle.gls_grid(phi, xl, xr, y, h2)).max() <= TOL[form]
+    check_bound(b, oracle.gls_grid(phi, xl, xr, y, h2), form, label="SNP stream n=%d p=%d" % (n, p))
 
 
 def test_snp_stream_argument_errors(torch_cuda):
