@@ -1,17 +1,19 @@
 """Benchmark of the GLS grid on one MI355X.
 
-A step is one pass of the whole hot path over the paper-shape workload
-(n = 1000 samples, p = 4, m = 100,000 SNPs, t = 1,000 traits, synthetic data
-drawn by `synth`): rotation of every SNP by Z^T (genotype bytes on the int8 MFMAs against Z in
-int8 digits, exact integer sums) and the solve
-of the 10^8-problem grid (trait rotation, per-trait prologue, fused
-contraction + FP64 p x p solve), with b left in HBM. Inputs (genotypes as
-uint8, traits as FP64) are resident in HBM before timing starts; the host
-eigendecomposition of the kinship matrix is setup and is not timed.
+A step is one pass of the whole hot path over the precision-study workload
+(n = 1000 samples, p = 4, m = 1,000,000 SNPs, t = 1,000 traits, synthetic data
+drawn by `synth`; the largest of the paper-shaped grids that stays resident on
+one GPU): rotation of every SNP by Z^T (genotype bytes on the int8 MFMAs
+against Z in int8 digits, exact integer sums) and the solve of the
+10^9-problem grid (trait rotation, per-trait prologue, fused contraction +
+FP64 p x p solve), with b left in HBM. Inputs (genotypes as uint8, traits as
+FP64) are resident in HBM before timing starts; the host eigendecomposition of
+the kinship matrix is setup and is not timed.
 
-The headline value is the FP32 form's throughput (GLS problems/s); the FP64
-and split-BF16 forms are timed the same way and reported beside it, each with
-its fused kernel's fraction of the MFMA peak of its own precision. A short run
+The headline value is the FP64 form's throughput (GLS problems/s), the
+paper's arithmetic; the FP32 and split-BF16 forms are timed the same way and
+reported beside it, each with its fused kernel's fraction of the MFMA peak of
+its own precision. A short run
 of the serving workload (500 requests at 16/s on a resident m = 1e6 cohort)
 adds the p50/p99 request latency under "serving". The
 oracle (plain FP64 C, dense Cholesky per problem) is timed on the host cores
@@ -34,17 +36,18 @@ sys.path.insert(0, ROOT)
 
 # MI355X published dense peaks
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}
-DEFAULT_FORMS = "f32,f64,bf16x3,bf16x6"
+DEFAULT_FORMS = "f64,f32,bf16x3,bf16x6"
 # BF16 MFMA products executed per algorithmic product
 MFMA_MULT = {"f64": 1, "f32": 1, "bf16x3": 3, "bf16x6": 6}
 HBM_GBPS = 8000.0
 
 
-def fused_traffic(form: str):
-    """HBM bytes per launch of the headline fused kernel from the committed counter
-    profile, or None when the kernel sources changed since the counters were taken."""
+def fused_traffic(form: str, workload: str):
+    """HBM bytes per launch of a form's fused kernel on a workload from the committed
+    counter profile, or None when there is none or the kernel sources changed since
+    the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "fused_%s_traffic_paper_m1e5.json" % form)
+    path = os.path.join(ROOT, "profiles", "fused_%s_traffic_%s.json" % (form, workload))
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -94,8 +97,8 @@ def cpu_baseline(w, phi, xl, budget_s: float = 12.0):
                 break
     except OSError:
         pass
-    # for context: the paper's own reduction (Algorithm 5: rotations by Z^T, then
-    # per trait the weighted products and a p x p solve per SNP) in numpy FP64 on
+    # for context: Eq. (1) through the eigendecomposition of Phi (rotations by
+    # Z^T, then per problem the weighted p x p normal equations) in numpy FP64 on
     # the same host, eigendecomposition excluded as setup
     from oracle import rotated
 
@@ -103,14 +106,16 @@ def cpu_baseline(w, phi, xl, budget_s: float = 12.0):
     mm, tt = 2000, 100
     xr_m = synth.snp_columns(w, rng.choice(w.m, size=mm, replace=False))
     t2 = time.perf_counter()
-    rotated.mt_gwas(xl, xr_m, y[:tt], h2[:tt], z, lam)
+    rotated.gls_rotated(xl, xr_m, y[:tt], h2[:tt], z, lam)
     dt2 = time.perf_counter() - t2
     return {"value": jj.size / dt, "unit": "GLS problems/s", "cores": threads, "kind": "oracle",
             "sample": "%d problems (i, j) of the %s workload (distinct SNPs, traits drawn at random), "
                       "each factorising its own n x n M_j; %.1f s on %d threads" % (jj.size, w.name, dt, threads),
             "single_thread_value": k1 / dt1, "cpu_model": model,
             "method_on_host": {"value": mm * tt / dt2, "unit": "GLS problems/s",
-                               "kind": "the paper's reduction (Algorithm 5) in numpy FP64, eigendecomposition excluded",
+                               "kind": "Eq. 1 through the eigendecomposition of Phi (rotate by Z^T, weighted "
+                                               "p x p normal equations per problem) in numpy FP64, "
+                                               "eigendecomposition excluded",
                                "sample": "%d SNPs x %d traits of the %s workload; %.2f s" % (mm, tt, w.name, dt2)}}
 
 
@@ -364,7 +369,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="paper_m1e5")
+    ap.add_argument("--workload", default="paper_m1e6")
     ap.add_argument("--forms", default=DEFAULT_FORMS, help="headline form first")
     ap.add_argument("--f32-flush", type=int, default=None,
                     help="FP32 form: 2 = FP64 folds (the library default), 0 = FP32 accumulation only")
@@ -492,6 +497,10 @@ def main():
             "paper_convention_tflops": cm.flops_per_gls_paper(w.n, w.p) * problems / (ms * 1e-3) / 1e12,
             "non_spd": st["non_spd"],
             "finite": bool(torch.isfinite(b).all()),
+            "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[form], "unit": "TFLOP/s",
+                         "frac": achieved / PEAK_TFLOPS[form], "traffic": fused_traffic(form, w.name),
+                         "flops_per_launch": mult * flops_gls * problems,
+                         "flops_counted": "executed BF16 products" if mult > 1 else "algorithmic"},
         }
         log("%s: %.3f ms/step (fused %.3f ms, rotate %.3f ms) -> %.3e GLS/s, fused %.1f TFLOP/s "
             "= %.1f%% of %s peak" % (form, ms, fused_ms, rot_ms, results[form]["gls_per_s"],
@@ -519,7 +528,7 @@ def main():
         "config": {"workload": w.name, "n": w.n, "p": w.p, "m": w.m, "t": w.t,
                    "form": head, "step": "rotate all SNPs + solve the full grid, b in HBM"},
         "roofline": {"bound": "mfma", "achieved": r["fused_tflops"], "peak": PEAK_TFLOPS[head],
-                     "unit": "TFLOP/s", "frac": r["mfma_frac"], "traffic": fused_traffic(head),
+                     "unit": "TFLOP/s", "frac": r["mfma_frac"], "traffic": fused_traffic(head, w.name),
                      "kernel": "fused_dma_kernel<%s, p=4>" % head,
                      "flops_per_launch": mult * flops_gls * problems},
         "forms": results,
