@@ -192,6 +192,27 @@ gwas_status gwas_solve(gwas_ctx *ctx, int64_t i0, int64_t mi, int32_t tb, const 
                        int32_t b_on_device, void *stream);
 
 /*
+ * gwas_solve for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and the same b, bitwise, but every per-call device buffer (staged
+ * and rotated traits, h2, trait panels, factors, tile counters) lives in a
+ * fixed 32 MiB array of the library in device memory, one per device, held
+ * until the process ends. The call allocates nothing, host or device.
+ * Arguments as gwas_solve, except that b must be device memory (mi x tb x p,
+ * FP64 for GWAS_FORM_F64 else FP32). The traits are processed in sub-blocks of
+ * as many traits as the array holds (at most the context's max_traits):
+ * about 56 KB per trait at n = 1000, p = 4, FP64 form. Every call on a device
+ * shares that device's array and leaves its last contents there: calls that
+ * overlap on one device (two host threads, or two streams not ordered by the
+ * caller) race and give wrong results. Statistics count the call's problems
+ * and non-SPD problems; its launches are not timed.
+ * Errors: as gwas_solve; GWAS_EINVAL if b is not device memory, or if a single
+ * trait's buffers exceed the array (not reachable for n <= 16384, p <= 20).
+ */
+gwas_status gwas_solve_noalloc(gwas_ctx *ctx, int64_t i0, int64_t mi, int32_t tb, const double *Y,
+                               int32_t y_on_device, const double *h2, int32_t form, void *b, void *stream);
+
+/*
  * Streamed solve (the b sink of the paper's double-buffering scheme, Section 4,
  * applied to the device->host link): the grid of SNPs [i0, i0 + mi) x the tb
  * traits of Y is solved as in gwas_solve, in slabs of gwas_options.slab_snps

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -121,6 +122,38 @@ int panel_planes(int form) { return form == GWAS_FORM_BF16X3 ? 2 : (form == GWAS
 
 }  // namespace
 
+// Scratch of gwas_solve_noalloc: one fixed array per device (each GPU the
+// library runs on holds its own copy until the process ends). It holds one
+// trait sub-block at a time (staged and rotated traits, h2, panels, factors,
+// tile counters); calls on one device share it.
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on device dev, which must be current. The
+// array's name in host code is a host-side stand-in, not a device address:
+// host code uses only the pointer obtained here.
+gwas_status noalloc_scratch(int dev, void **ptr) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(GWAS_EINVAL, "device %d outside [0, %d)", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(GWAS_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return GWAS_OK;
+}
+
+}  // namespace
+
 namespace gw {
 hipError_t launch_fused(int form, const FusedArgs &a, hipStream_t s) {
     switch (form) {
@@ -175,6 +208,11 @@ gwas_status gwas_setup(gwas_ctx **out, int32_t n, int32_t p, const double *Z, co
     }
     c->dev = dev;
     if (hipSetDevice(dev) != hipSuccess) { delete c; return fail(GWAS_EINVAL, "bad device %d", dev); }
+    {   // the device's address of the no-allocation scratch, taken once per device
+        void *sp = nullptr;
+        gwas_status sst = noalloc_scratch(dev, &sp);
+        if (sst != GWAS_OK) { delete c; return sst; }
+    }
     c->n = n;
     c->n_pad = (int)round_up(n, kPadN);
     c->p = p;
@@ -332,44 +370,66 @@ gwas_status check_solve(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, const d
     return GWAS_OK;
 }
 
+// Device memory of a trait sub-block: staged traits, rotated traits, h2, the
+// form's panels (plane stride tcap rows), factors, persistent tile counters.
+struct TraitScratch {
+    double *y_in, *yt, *h2, *fac;
+    void *panels;
+    unsigned *tile_counters;
+    int tcap;
+};
+
+TraitScratch ctx_scratch(gwas_ctx *c, int32_t form) {
+    return TraitScratch{c->y_in, c->yt, c->h2, c->fac, c->panels[form], (unsigned *)(c->counters + 4), c->tcap};
+}
+
 // Trait sub-block [j0, j0 + jb): stage, rotate y' = Z^T y (FP64), and run the
-// per-trait prologue into the context's panels and factors.
-gwas_status prep_traits(gwas_ctx *c, int j0, int jb, const double *Y, int32_t y_on_device, const double *h2,
-                        int32_t form, hipStream_t s) {
+// per-trait prologue into the scratch's panels and factors.
+gwas_status prep_traits(gwas_ctx *c, const TraitScratch &ts, int j0, int jb, const double *Y, int32_t y_on_device,
+                        const double *h2, int32_t form, hipStream_t s) {
     const double *ysrc = Y + (size_t)j0 * c->n;
     if (!y_on_device) {
-        HIP_TRY(hipMemcpyAsync(c->y_in, ysrc, sizeof(double) * (size_t)jb * c->n, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(ts.y_in, ysrc, sizeof(double) * (size_t)jb * c->n, hipMemcpyHostToDevice, s));
         c->bytes_h2d += (int64_t)sizeof(double) * jb * c->n;
-        ysrc = c->y_in;
+        ysrc = ts.y_in;
     }
-    HIP_TRY(hipMemcpyAsync(c->h2, h2 + j0, sizeof(double) * jb, hipMemcpyHostToDevice, s));
-    RotOut ro{c->yt, nullptr, nullptr, nullptr, 0, 0, c->n_pad};
+    HIP_TRY(hipMemcpyAsync(ts.h2, h2 + j0, sizeof(double) * jb, hipMemcpyHostToDevice, s));
+    RotOut ro{ts.yt, nullptr, nullptr, nullptr, 0, 0, c->n_pad};
     HIP_TRY(launch_rotate(ysrc, GWAS_DT_F64, jb, c->n, c->n, c->Z, c->n_pad, ro, s));
-    PrepArgs pa{c->yt, c->h2, c->w, c->xlt, c->panels[form], c->fac, jb, c->n, c->n_pad, c->p, c->tcap,
+    PrepArgs pa{ts.yt, ts.h2, c->w, c->xlt, ts.panels, ts.fac, jb, c->n, c->n_pad, c->p, ts.tcap,
                 fac_stride(c->p), form};
     HIP_TRY(launch_prep(pa, s));
     return GWAS_OK;
 }
 
-FusedArgs fused_args(gwas_ctx *c, int jb, int32_t form, int tb_call) {
+gwas_status prep_traits(gwas_ctx *c, int j0, int jb, const double *Y, int32_t y_on_device, const double *h2,
+                        int32_t form, hipStream_t s) {
+    return prep_traits(c, ctx_scratch(c, form), j0, jb, Y, y_on_device, h2, form, s);
+}
+
+FusedArgs fused_args(gwas_ctx *c, const TraitScratch &ts, int jb, int32_t form, int tb_call) {
     FusedArgs fa{};
     fa.a = form == GWAS_FORM_F64 ? (const void *)c->xr64
          : form == GWAS_FORM_F32 ? (const void *)c->xr32
          : form == GWAS_FORM_BF16X3 ? (const void *)c->xrbf : (const void *)c->xrbf3;
     fa.a_plane_rows = c->m_rows;
-    fa.panels = c->panels[form];
-    fa.tcap = c->tcap;
-    fa.fac = c->fac;
+    fa.panels = ts.panels;
+    fa.tcap = ts.tcap;
+    fa.fac = ts.fac;
     fa.fac_stride = fac_stride(c->p);
     fa.tb = jb;
     fa.n_pad = c->n_pad;
     fa.p = c->p;
     fa.rank_rtol = kRankRtol[form];
     fa.non_spd = c->counters;
-    fa.tile_counters = (unsigned *)(c->counters + 4);
+    fa.tile_counters = ts.tile_counters;
     fa.f32_flush = form == GWAS_FORM_F32 ? c->f32_flush : 0;
     fa.small_t = use_dot_kernel(form, c->p, tb_call, c->n_pad);
     return fa;
+}
+
+FusedArgs fused_args(gwas_ctx *c, int jb, int32_t form, int tb_call) {
+    return fused_args(c, ctx_scratch(c, form), jb, form, tb_call);
 }
 
 gwas_status launch_fused_timed(gwas_ctx *c, int32_t form, const FusedArgs &fa, hipStream_t s) {
@@ -448,6 +508,69 @@ gwas_status gwas_solve(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, const do
             HIP_TRY(hipEventRecord(c->ev_side, c->side));
             HIP_TRY(hipStreamWaitEvent(s, c->ev_side, 0));
         }
+    }
+    c->problems += mi * (int64_t)tb;
+    return GWAS_OK;
+}
+
+gwas_status gwas_solve_noalloc(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, const double *Y,
+                               int32_t y_on_device, const double *h2, int32_t form, void *b, void *stream) {
+    last_error().clear();
+    gwas_status st = check_solve(c, i0, mi, tb, Y, y_on_device, h2, form);
+    if (st != GWAS_OK) return st;
+    if (mi > 0 && !b) return fail(GWAS_EINVAL, "b is NULL");
+    if (mi == 0) return GWAS_OK;
+    HIP_TRY(hipSetDevice(c->dev));
+    {
+        hipPointerAttribute_t at{};
+        hipError_t e = hipPointerGetAttributes(&at, b);
+        if (e != hipSuccess || at.type != hipMemoryTypeDevice) {
+            (void)hipGetLastError();   // a host pointer leaves an error code behind
+            return fail(GWAS_EINVAL, "b must be device memory");
+        }
+    }
+    void *base = nullptr;
+    if ((st = noalloc_scratch(c->dev, &base)) != GWAS_OK) return st;
+    // the largest trait sub-block whose regions (each rounded to 256 bytes) fit the array
+    const int p = c->p, np = c->n_pad;
+    auto r256 = [](size_t v) { return (size_t)round_up((int64_t)v, 256); };
+    auto need = [&](int jb) {
+        return r256(8 * sizeof(unsigned)) + (y_on_device ? 0 : r256(sizeof(double) * (size_t)jb * c->n)) +
+               r256(sizeof(double) * (size_t)jb * np) + r256(sizeof(double) * jb) +
+               r256(sizeof(double) * (size_t)jb * fac_stride(p)) +
+               r256(elt_size(form) * (size_t)panel_planes(form) * (p + 1) * jb * np);
+    };
+    if (need(1) > kNoAllocScratchBytes)
+        return fail(GWAS_EINVAL, "one trait needs %zu scratch bytes at n = %d, p = %d, above the %zu of the array",
+                    need(1), c->n, p, kNoAllocScratchBytes);
+    int jmax = std::min(tb, c->tcap);
+    while (need(jmax) > kNoAllocScratchBytes) jmax = std::max(1, (int)((int64_t)jmax * kNoAllocScratchBytes / need(jmax)) - 1);
+    uint8_t *q = (uint8_t *)base;
+    auto take = [&](size_t bytes) {
+        uint8_t *r = q;
+        q += r256(bytes);
+        return (void *)r;
+    };
+    TraitScratch ts{};
+    ts.tcap = jmax;
+    ts.tile_counters = (unsigned *)take(8 * sizeof(unsigned));
+    ts.y_in = y_on_device ? nullptr : (double *)take(sizeof(double) * (size_t)jmax * c->n);
+    ts.yt = (double *)take(sizeof(double) * (size_t)jmax * np);
+    ts.h2 = (double *)take(sizeof(double) * jmax);
+    ts.fac = (double *)take(sizeof(double) * (size_t)jmax * fac_stride(p));
+    ts.panels = take(elt_size(form) * (size_t)panel_planes(form) * (p + 1) * jmax * np);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t besz = form == GWAS_FORM_F64 ? 8 : 4;
+    for (int j0 = 0; j0 < tb; j0 += jmax) {
+        const int jb = std::min(jmax, tb - j0);
+        if ((st = prep_traits(c, ts, j0, jb, Y, y_on_device, h2, form, s)) != GWAS_OK) return st;
+        FusedArgs fa = fused_args(c, ts, jb, form, tb);
+        fa.i0 = i0;
+        fa.mi = mi;
+        fa.b = (uint8_t *)b + (size_t)j0 * p * besz;
+        fa.ldt = tb;
+        HIP_TRY(launch_fused(form, fa, s));
+        if (fa.small_t) ++c->dot_launches;
     }
     c->problems += mi * (int64_t)tb;
     return GWAS_OK;

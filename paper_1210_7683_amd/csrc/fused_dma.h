@@ -393,6 +393,13 @@ __global__ __launch_bounds__((DmaCfg<FORM, P, T>::NT)) void fused_dma_persistent
     }
 }
 
+// Clears the persistent launch's 8 tile counters with a kernel (a memset node
+// is not what a caller capturing the stream into a graph should get).
+template <int N>
+__global__ void zero_words_kernel(unsigned *w) {
+    if (threadIdx.x < N) w[threadIdx.x] = 0u;
+}
+
 template <int FORM, int P, bool FLUSH, class T>
 hipError_t launch_dma_t(const FusedArgs &a, hipStream_t s) {
     using C = DmaCfg<FORM, P, T>;
@@ -411,8 +418,8 @@ hipError_t launch_dma_t(const FusedArgs &a, hipStream_t s) {
         int dev = 0, cus = 256;
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e == hipSuccess) e = hipMemsetAsync(a.tile_counters, 0, 8 * sizeof(unsigned), s);
         if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(zero_words_kernel<8>, dim3(1), dim3(64), 0, s, a.tile_counters);
         const int64_t grid = std::max<int64_t>(8, std::min<int64_t>(cus, (tiles + 7) / 8 * 8));
         hipLaunchKernelGGL((fused_dma_persistent_kernel<FORM, P, FLUSH, T>), dim3((unsigned)grid), dim3(C::NT),
                            C::LDS, s, a);

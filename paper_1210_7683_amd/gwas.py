@@ -106,6 +106,8 @@ def load():
     lib.gwas_rotate.restype = i32
     lib.gwas_solve.argtypes = [vp, i64, i64, i32, vp, i32, vp, i32, vp, i32, vp]
     lib.gwas_solve.restype = i32
+    lib.gwas_solve_noalloc.argtypes = [vp, i64, i64, i32, vp, i32, vp, i32, vp, vp]
+    lib.gwas_solve_noalloc.restype = i32
     lib.gwas_solve_stream.argtypes = [vp, i64, i64, i32, vp, i32, vp, i32, SLAB_FN, vp,
                                       ctypes.POINTER(ctypes.c_uint64), i64, ctypes.POINTER(i64), vp]
     lib.gwas_solve_stream.restype = i32
@@ -290,6 +292,27 @@ class Cohort:
             raise ValueError("out must be a contiguous %s tensor of shape %s" % (dt, (m, t, self.p)))
         _check(lib.gwas_solve(self._h, int(i0), m, t, yp, ydev, h2.ctypes.data, f,
                               ctypes.c_void_p(out.data_ptr()), int(out.is_cuda), _stream_ptr(stream)))
+        self._keep = (ykeep, h2)
+        return out
+
+    def solve_noalloc(self, y, h2, out, form: str = "f32", i0: int = 0, stream=None):
+        """gwas_solve_noalloc: b for SNPs [i0, i0 + out.shape[0]) and traits y [t][n]
+        into `out`, a preallocated contiguous device tensor [m][t][p]; the library
+        allocates nothing (its per-call buffers live in a fixed device array)."""
+        import torch
+        f = FORMS[form]
+        m, t = int(out.shape[0]), int(y.shape[0])
+        h2 = np.ascontiguousarray(h2, dtype=np.float64)
+        if h2.shape != (t,):
+            raise ValueError("h2 needs one value per trait")
+        if _is_device(y) and y.dtype != torch.float64:
+            raise ValueError("device traits must be float64")
+        yp, ydev, ykeep = _ptr(y if _is_device(y) else np.ascontiguousarray(y, dtype=np.float64))
+        dt = torch.float64 if f == FORM_F64 else torch.float32
+        if not out.is_cuda or out.dtype != dt or tuple(out.shape) != (m, t, self.p) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous device %s tensor of shape %s" % (dt, (m, t, self.p)))
+        _check(load().gwas_solve_noalloc(self._h, int(i0), m, t, yp, ydev, h2.ctypes.data, f,
+                                         ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         self._keep = (ykeep, h2)
         return out
 
