@@ -184,10 +184,12 @@ def stream_bench(args):
 
 
 def single_trait_bench(args):
-    """One trait (t = 1) against m = 1e6 resident SNPs, n = 1000, p = 4: the
-    dot-product kernel, bound by reading the rotated SNP store once. A step is
-    one solve of the m x 1 grid (the rotation is the cohort's one-time setup,
-    timed separately); the roofline is HBM bytes per launch over its duration."""
+    """Few traits (t = 1, 2, 3) against m = 1e6 resident SNPs, n = 1000, p = 4:
+    the dot-product kernel, bound by reading the rotated SNP store once. A step
+    is one solve of the m x t grid (the rotation is the cohort's one-time setup,
+    timed separately); the roofline is HBM bytes per launch over its duration.
+    The headline is t = 1; traits beyond the workload's one come from the same
+    generator (the paper-shape workload's first traits)."""
     import torch
 
     import synth
@@ -195,12 +197,16 @@ def single_trait_bench(args):
 
     w = synth.WORKLOADS[args.workload]
     forms = [f for f in args.forms.split(",") if f in ("f32", "f64")] or ["f32"]
+    ts = [int(v) for v in args.small_t.split(",")]
     t0 = time.perf_counter()
     phi, xl = synth.kinship(w), synth.covariates(w)
     xr = synth.snps(w)
     y, h2 = synth.traits(w)
+    if max(ts) > w.t:
+        y2, h22 = synth.traits("paper_m1e6", 0, max(ts) - w.t)
+        y, h2 = np.vstack([y, y2]), np.concatenate([h2, h22])
     ev, z = np.linalg.eigh(phi)
-    log("inputs (%d SNPs, %d trait) drawn in %.1f s" % (w.m, w.t, time.perf_counter() - t0))
+    log("inputs (%d SNPs, %d traits) drawn in %.1f s" % (w.m, y.shape[0], time.perf_counter() - t0))
     xr_d = torch.from_numpy(xr).cuda()
     y_d = torch.from_numpy(y).cuda()
     results = {}
@@ -208,42 +214,46 @@ def single_trait_bench(args):
         cohort = gwas.Cohort(z, ev, xl, w.m, forms=(form,), timing=True)
         cohort.rotate(0, xr_d)
         dt = torch.float64 if form == "f64" else torch.float32
-        b = torch.empty((w.m, w.t, w.p), dtype=dt, device="cuda")
         torch.cuda.synchronize()
         rot_ms = cohort.stats()["rotate_ms"]
-        for _ in range(args.warmup):
-            cohort.solve(y_d, h2, form=form, out=b)
-        torch.cuda.synchronize()
-        cohort.reset_stats()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(args.steps):
-            cohort.solve(y_d, h2, form=form, out=b)
-        e1.record()
-        torch.cuda.synchronize()
-        st = cohort.stats()
-        ms = e0.elapsed_time(e1) / args.steps
-        fused_ms = st["fused_ms"] / max(1, st["fused_launches"])
-        esz = 8 if form == "f64" else 4
-        bytes_launch = w.m * (w.n * esz + w.t * w.p * esz)   # X'_R rows once + b
-        results[form] = {"gls_per_s": w.m * w.t / (ms * 1e-3), "ms_per_step": ms, "fused_ms": fused_ms,
-                         "hbm_gbps": bytes_launch / (fused_ms * 1e-3) / 1e9, "dot_launches": st["dot_launches"],
-                         "rotate_once_ms": rot_ms, "finite": bool(torch.isfinite(b).all().item())}
-        log("%s: %.3f ms/solve (kernel %.3f ms, %.0f GB/s), %.3g GLS/s; rotation once %.1f ms" %
-            (form, ms, fused_ms, results[form]["hbm_gbps"], results[form]["gls_per_s"], rot_ms))
+        for t in ts:
+            b = torch.empty((w.m, t, w.p), dtype=dt, device="cuda")
+            for _ in range(args.warmup):
+                cohort.solve(y_d[:t], h2[:t], form=form, out=b)
+            torch.cuda.synchronize()
+            cohort.reset_stats()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                cohort.solve(y_d[:t], h2[:t], form=form, out=b)
+            e1.record()
+            torch.cuda.synchronize()
+            st = cohort.stats()
+            ms = e0.elapsed_time(e1) / args.steps
+            fused_ms = st["fused_ms"] / max(1, st["fused_launches"])
+            esz = 8 if form == "f64" else 4
+            bytes_launch = w.m * (w.n * esz + t * w.p * esz)   # X'_R rows once + b
+            key = form if t == ts[0] else "%s_t%d" % (form, t)
+            results[key] = {"t": t, "gls_per_s": w.m * t / (ms * 1e-3), "ms_per_step": ms, "fused_ms": fused_ms,
+                            "hbm_gbps": bytes_launch / (fused_ms * 1e-3) / 1e9,
+                            "dot_launches": st["dot_launches"] // max(1, args.steps),
+                            "rotate_once_ms": rot_ms, "finite": bool(torch.isfinite(b).all().item())}
+            log("%s t=%d: %.3f ms/solve (kernel %.3f ms, %.0f GB/s), %.3g GLS/s, dot kernel %s; rotation once %.1f ms" %
+                (form, t, ms, fused_ms, results[key]["hbm_gbps"], results[key]["gls_per_s"],
+                 bool(st["dot_launches"]), rot_ms))
+            del b
         cohort.close()
-        del b
     head = forms[0]
     r = results[head]
     line = {"metric": "GLS problems/s, single trait (t = 1) against a resident cohort",
             "value": r["gls_per_s"], "unit": "GLS problems/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": head, "data": "synthetic",
-            "config": {"workload": w.name, "n": w.n, "p": w.p, "m": w.m, "t": w.t, "form": head,
-                       "step": "solve of the m x 1 grid, rotated SNPs resident, b in HBM"},
+            "config": {"workload": w.name, "n": w.n, "p": w.p, "m": w.m, "t": r["t"], "form": head,
+                       "step": "solve of the m x t grid, rotated SNPs resident, b in HBM"},
             "roofline": {"bound": "hbm", "achieved": r["hbm_gbps"], "peak": HBM_GBPS, "unit": "GB/s",
                          "frac": r["hbm_gbps"] / HBM_GBPS, "traffic": None,
-                         "kernel": "fused_gemv_kernel<%s, p=4, t=1>" % head},
+                         "kernel": "fused_gemv_kernel<%s, p=4, t=%d>" % (head, r["t"])},
             "forms": results}
     print(json.dumps(line), flush=True)
 
@@ -378,6 +388,7 @@ def main():
                     help="paper-shape bench: skip the short serving run that reports p50/p99 latency")
     ap.add_argument("--serving-requests", type=int, default=500,
                     help="paper-shape bench: measured requests of the short serving run")
+    ap.add_argument("--small-t", default="1,2,3", help="single_trait workload: trait counts to time")
     ap.add_argument("--rate", type=float, default=16.0, help="serving: request arrival rate (1/s)")
     ap.add_argument("--requests", type=int, default=200, help="serving: measured requests")
     ap.add_argument("--warmup-requests", type=int, default=20)

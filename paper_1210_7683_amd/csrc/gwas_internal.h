@@ -188,13 +188,14 @@ struct FusedArgs {
 hipError_t launch_fused(int form, const FusedArgs &a, hipStream_t s);
 
 // FP64 and FP32 solve calls with at most kSmallT traits in total, whose panels
-// fit the dot-product kernel's LDS copy, use that kernel (HBM-bound,
-// fused_gemv.h) instead of the MFMA tiles; measured on MI355X at n = 1000,
-// p = 4, it is faster there (the split-BF16 MFMA tiles are not slower at any
-// t, and both split-BF16 forms keep them). The choice is per call, so every problem of a call is computed the same
-// way whatever the sub-blocking.
+// fit the dot-product kernel's LDS copy (a CU's 160 KB), use that kernel
+// (HBM-bound, fused_gemv.h) instead of the MFMA tiles; measured on MI355X at
+// n = 1000, p = 4, it is faster there (the split-BF16 MFMA tiles are not
+// slower at any t, and both split-BF16 forms keep them). The choice is per
+// call, so every problem of a call is computed the same way whatever the
+// sub-blocking.
 constexpr int kSmallT = 3;
-constexpr int64_t kGemvLdsMax = 64 * 1024;
+constexpr int64_t kGemvLdsMax = 160 * 1024;
 inline bool use_dot_kernel(int form, int p, int tb_call, int n_pad) {
     const int64_t lds = (int64_t)(p + 1) * tb_call * n_pad * (form == GWAS_FORM_F64 ? 8 : 4);
     return (form == GWAS_FORM_F64 || form == GWAS_FORM_F32) && tb_call <= kSmallT && lds <= kGemvLdsMax;

@@ -193,20 +193,23 @@ def test_fp32_without_fp64_folds(torch_cuda):
 
 @pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("n,p,m,t", [(200, 2, 333, 1), (77, 4, 100, 2), (130, 9, 129, 3),
-                                     (1000, 4, 70, 1), (1000, 4, 70, 4), (64, 20, 40, 1),
+                                     (1000, 4, 70, 1), (1000, 4, 70, 2), (1000, 4, 1100, 3),
+                                     (1000, 9, 70, 3), (1000, 4, 70, 4), (64, 20, 40, 1),
                                      (96, 13, 65, 3)])
 def test_small_trait_calls_use_the_dot_product_kernel(form, n, p, m, t, torch_cuda):
-    """FP64 and FP32 solve calls with t <= 3 traits whose panels fit 64 KB run
-    the dot-product kernel (counted in the stats); every case: parity with the
-    oracle at the form's tolerance, ragged m and n, and the device, sub-range and
-    host-slab outputs agree bitwise."""
+    """FP64 and FP32 solve calls with t <= 3 traits whose panels fit the 160 KB
+    of LDS run the dot-product kernel (counted in the stats): with 256-thread
+    workgroups while the panels take at most 40 KB, else 1024 (n = 1000, p = 4:
+    FP64 t = 2, 3 and FP32 t = 3); FP64 at p = 9, t = 3 (240 KB) keeps the MFMA
+    tiles. Every case: parity with the oracle at the form's tolerance, ragged m
+    and n, and the device, sub-range and host-slab outputs agree bitwise."""
     torch = torch_cuda
     phi, xl, xr, y, h2 = synth.small(n, p, m, t, seed=n * 7 + p + t)
     ref = oracle.gls_grid(phi, xl, xr, y, h2)
     c = cohort(phi, xl, xr, forms=(form,), slab_snps=32)
     b = c.solve(y, h2, form=form).cpu().numpy()
     n_pad = (n + 63) // 64 * 64
-    dot = form in ("f64", "f32") and t <= 3 and (p + 1) * t * n_pad * (8 if form == "f64" else 4) <= 64 * 1024
+    dot = form in ("f64", "f32") and t <= 3 and (p + 1) * t * n_pad * (8 if form == "f64" else 4) <= 160 * 1024
     assert c.stats()["dot_launches"] == (1 if dot else 0)
     check_bound(b, ref, form, label="n=%d p=%d m=%d t=%d" % (n, p, m, t))
     part = c.solve(y, h2, form=form, i0=3, m=m - 5).cpu().numpy()
