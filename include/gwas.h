@@ -288,7 +288,11 @@ gwas_status gwas_copy_rotated(gwas_ctx *ctx, int64_t i0, int64_t mi, int32_t for
  *   GWAS_DBG_FAC     per-trait factors of the last sub-block: tcap x S FP64 with
  *                    S = even(q(q+1)/2 + q), q = p-1: packed L_j^{-1} (row-major
  *                    lower), then z_j = L_j^{-1} b_T_j
- *   GWAS_DBG_PANELS  trait panels of the last sub-block in the form's layout
+ *   GWAS_DBG_PANELS  trait panels of the last sub-block in the form's layout:
+ *                    per plane max_traits rounded up to 16 rows of n_pad values,
+ *                    row-major (FP64, FP32) or, for the split-BF16 forms, in MFMA
+ *                    fragment order (1 KB block (row / 16, k / 32) holds lane
+ *                    L = (k mod 32) / 8 * 16 + row mod 16 at bytes 16 L .. 16 L + 15)
  * bytes must equal the buffer's size (gwas_debug_size reports it).
  */
 #define GWAS_DBG_XL 0

@@ -155,7 +155,15 @@ gwas_status noalloc_scratch(int dev, void **ptr) {
 }  // namespace
 
 namespace gw {
-hipError_t launch_fused(int form, const FusedArgs &a, hipStream_t s) {
+hipError_t launch_fused(int form, const FusedArgs &a0, hipStream_t s) {
+    FusedArgs a = a0;
+    if ((form == GWAS_FORM_BF16X3 || form == GWAS_FORM_BF16X6) && (a.i0 & 15)) {
+        // the fragment-ordered store is staged by whole 16-row groups: start the
+        // range at the group and leave its first rows unstored
+        a.row_lo = a.i0 & 15;
+        a.i0 -= a.row_lo;
+        a.mi += a.row_lo;
+    }
     switch (form) {
     case GWAS_FORM_F64: return launch_fused_f64(a, s);
     case GWAS_FORM_F32: return launch_fused_f32(a, s);
@@ -248,7 +256,7 @@ gwas_status gwas_setup(gwas_ctx **out, int32_t n, int32_t p, const double *Z, co
     for (int f = 0; f < 4; ++f)
         if (forms & GWAS_FORM_BIT(f)) {
             const size_t planes = (size_t)panel_planes(f) * (p + 1);
-            TRY(dalloc(c, &c->panels[f], elt_size(f) * planes * c->tcap * np));
+            TRY(dalloc(c, &c->panels[f], elt_size(f) * planes * panel_rows(c->tcap) * np));
         }
     TRY(dalloc(c, &c->fac, sizeof(double) * (size_t)c->tcap * fac_stride(p)));
     // [0..3] statistics, [4..7] the 8 tile counters of persistent launches
@@ -371,7 +379,8 @@ gwas_status check_solve(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, const d
 }
 
 // Device memory of a trait sub-block: staged traits, rotated traits, h2, the
-// form's panels (plane stride tcap rows), factors, persistent tile counters.
+// form's panels (plane stride tcap rows, a multiple of 16), factors, persistent
+// tile counters.
 struct TraitScratch {
     double *y_in, *yt, *h2, *fac;
     void *panels;
@@ -380,7 +389,8 @@ struct TraitScratch {
 };
 
 TraitScratch ctx_scratch(gwas_ctx *c, int32_t form) {
-    return TraitScratch{c->y_in, c->yt, c->h2, c->fac, c->panels[form], (unsigned *)(c->counters + 4), c->tcap};
+    return TraitScratch{c->y_in, c->yt, c->h2, c->fac, c->panels[form], (unsigned *)(c->counters + 4),
+                        panel_rows(c->tcap)};
 }
 
 // Trait sub-block [j0, j0 + jb): stage, rotate y' = Z^T y (FP64), and run the
@@ -538,7 +548,7 @@ gwas_status gwas_solve_noalloc(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, 
         return r256(8 * sizeof(unsigned)) + (y_on_device ? 0 : r256(sizeof(double) * (size_t)jb * c->n)) +
                r256(sizeof(double) * (size_t)jb * np) + r256(sizeof(double) * jb) +
                r256(sizeof(double) * (size_t)jb * fac_stride(p)) +
-               r256(elt_size(form) * (size_t)panel_planes(form) * (p + 1) * jb * np);
+               r256(elt_size(form) * (size_t)panel_planes(form) * (p + 1) * panel_rows(jb) * np);
     };
     if (need(1) > kNoAllocScratchBytes)
         return fail(GWAS_EINVAL, "one trait needs %zu scratch bytes at n = %d, p = %d, above the %zu of the array",
@@ -552,13 +562,13 @@ gwas_status gwas_solve_noalloc(gwas_ctx *c, int64_t i0, int64_t mi, int32_t tb, 
         return (void *)r;
     };
     TraitScratch ts{};
-    ts.tcap = jmax;
+    ts.tcap = panel_rows(jmax);
     ts.tile_counters = (unsigned *)take(8 * sizeof(unsigned));
     ts.y_in = y_on_device ? nullptr : (double *)take(sizeof(double) * (size_t)jmax * c->n);
     ts.yt = (double *)take(sizeof(double) * (size_t)jmax * np);
     ts.h2 = (double *)take(sizeof(double) * jmax);
     ts.fac = (double *)take(sizeof(double) * (size_t)jmax * fac_stride(p));
-    ts.panels = take(elt_size(form) * (size_t)panel_planes(form) * (p + 1) * jmax * np);
+    ts.panels = take(elt_size(form) * (size_t)panel_planes(form) * (p + 1) * ts.tcap * np);
     hipStream_t s = (hipStream_t)stream;
     const size_t besz = form == GWAS_FORM_F64 ? 8 : 4;
     for (int j0 = 0; j0 < tb; j0 += jmax) {
@@ -884,7 +894,7 @@ int64_t gwas_debug_size(gwas_ctx *c, int32_t what, int32_t form) {
     case GWAS_DBG_FAC: return (int64_t)sizeof(double) * c->tcap * fac_stride(c->p);
     case GWAS_DBG_PANELS:
         if (form < 0 || form > 3 || !(c->forms & GWAS_FORM_BIT(form))) return -1;
-        return (int64_t)elt_size(form) * panel_planes(form) * (c->p + 1) * c->tcap * np;
+        return (int64_t)elt_size(form) * panel_planes(form) * (c->p + 1) * panel_rows(c->tcap) * np;
     default: return -1;
     }
 }

@@ -50,8 +50,8 @@ __device__ __forceinline__ void square_split(const bf16x8 &h, const bf16x8 &l, b
 //   u = L_j^{-1} S_BL;  s = S_BR - u.u;  beta = (b_B - u.z_j) / s;
 //   b_top = L_j^{-T} (z_j - u beta)
 // with Lf(k) the packed lower triangle of L_j^{-1} and z = z_j. Stores b_ij
-// (NaN when the pivot s falls below rank_rtol * S_BR or is not finite) and
-// returns whether it was finite.
+// (NaN when the pivot s falls below rank_rtol * S_BR or is not finite) at row
+// i - row_lo of b and returns whether it was finite.
 template <int FORM, int P, class LF>
 __device__ __forceinline__ bool gls_solve_store(const FusedArgs &a, const double *cq, LF Lf, const double *z,
                                                 int64_t i, int j) {
@@ -82,7 +82,7 @@ __device__ __forceinline__ bool gls_solve_store(const FusedArgs &a, const double
         out[bb] = v;
     }
     out[Q] = beta;
-    const int64_t o = (i * a.ldt + j) * P;
+    const int64_t o = ((i - a.row_lo) * a.ldt + j) * P;
     if constexpr (FORM == GWAS_FORM_F64) {
         double *bo = (double *)a.b + o;
 #pragma unroll
@@ -144,7 +144,7 @@ __device__ __forceinline__ void fused_epilogue(const FusedArgs &a, Get get, int6
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t i = m_base + wm * FM * 16 + x * 16 + mfma16_row<FORM == GWAS_FORM_F64>(g, r);
-                if (i >= a.mi) continue;
+                if (i >= a.mi || i < a.row_lo) continue;
                 double cq[P + 1];
 #pragma unroll
                 for (int q = 0; q <= P; ++q) cq[q] = get(q, x, y, r);

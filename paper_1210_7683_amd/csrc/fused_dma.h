@@ -22,7 +22,8 @@
 //
 // Split BF16: only the pieces of x' are staged (hi, lo; or hi, mid, lo); the
 // split of x'^2 is formed from them in registers (square_split,
-// square_split3), which halves the SNP-side bytes.
+// square_split3), which halves the SNP-side bytes. Their planes are stored in
+// fragment order (bf_frag_index), so every block is one contiguous 1 KB copy.
 // FP64 folds (FLUSH): FP32 accumulators are added to FP64 sums at the end of
 // each window and the next window's first MFMA starts from zero. FP32 form
 // (KB = 2, 8 MFMAs of 4 samples per sum and stage): b_B, the sum that cancels,
@@ -134,6 +135,11 @@ __device__ __forceinline__ void dma_tile(const FusedArgs &a, int64_t tile, uint8
     // group, blocks [0, GA) are the SNP planes (plane-major, 16-row groups), the
     // rest the trait planes. Rows past the tile's range are clamped into it:
     // they only feed outputs that are never stored.
+    // The split-BF16 planes are fragment-ordered (bf_frag_index): a block is one
+    // contiguous 1 KB source, the 16-row (16-trait) group clamped to the last
+    // group in range (a.i0 + m_base is a multiple of 16, see launch_fused), the
+    // same per-lane offset for every block, and a stage advances by KB blocks.
+    const int nkg = a.n_pad / 32;
     const uint8_t *sbase[C::LPW];
     uint32_t voff[C::LPW];
 #pragma unroll
@@ -145,26 +151,39 @@ __device__ __forceinline__ void dma_tile(const FusedArgs &a, int64_t tile, uint8
             const int kb = blk / C::GBK, r = blk % C::GBK;
             if (r < C::GA) {
                 const int pl = r / (TM / 16), rg = r % (TM / 16);
-                int64_t i = m_base + rg * 16 + l16;
-                if (i >= a.mi) i = a.mi - 1;
-                sbase[u] = A + pl * a_plane + (a.i0 + m_base) * row_bytes + kb * 64;
-                voff[u] = (uint32_t)((i - m_base) * row_bytes) + g * 16;
+                if constexpr (BF) {
+                    const int64_t grp = min((a.i0 + m_base) / 16 + rg, (a.i0 + a.mi - 1) / 16);
+                    sbase[u] = A + pl * a_plane + (grp * nkg + kb) * 1024;
+                    voff[u] = lane * 16;
+                } else {
+                    int64_t i = m_base + rg * 16 + l16;
+                    if (i >= a.mi) i = a.mi - 1;
+                    sbase[u] = A + pl * a_plane + (a.i0 + m_base) * row_bytes + kb * 64;
+                    voff[u] = (uint32_t)((i - m_base) * row_bytes) + g * 16;
+                }
             } else {
                 const int rb = r - C::GA;
                 const int pl = rb / (TN / 16), cg = rb % (TN / 16);
-                int j = n_base + cg * 16 + l16;
-                if (j >= a.tb) j = a.tb - 1;
-                sbase[u] = B + pl * b_plane + (int64_t)n_base * row_bytes + kb * 64;
-                voff[u] = (uint32_t)((j - n_base) * row_bytes) + g * 16;
+                if constexpr (BF) {
+                    const int grp = min(n_base / 16 + cg, (a.tb - 1) / 16);
+                    sbase[u] = B + pl * b_plane + ((int64_t)grp * nkg + kb) * 1024;
+                    voff[u] = lane * 16;
+                } else {
+                    int j = n_base + cg * 16 + l16;
+                    if (j >= a.tb) j = a.tb - 1;
+                    sbase[u] = B + pl * b_plane + (int64_t)n_base * row_bytes + kb * 64;
+                    voff[u] = (uint32_t)((j - n_base) * row_bytes) + g * 16;
+                }
             }
         }
     }
+    constexpr int STAGE_STRIDE = BF ? KB * 1024 : KB * 64;   // source bytes from one stage to the next
     auto issue = [&](int c) {
         uint8_t *stage = lds + (C::PIPE ? (c & 1) * (C::BLK * 1024) : 0);
 #pragma unroll
         for (int u = 0; u < C::LPW; ++u) {
             const int blk = wave + u * C::NW;
-            if (blk < C::BLK) lds_dma16(sbase[u] + (int64_t)c * (KB * 64) + voff[u], stage + blk * 1024);
+            if (blk < C::BLK) lds_dma16(sbase[u] + (int64_t)c * STAGE_STRIDE + voff[u], stage + blk * 1024);
         }
     };
     auto afrag = [&](int kb, int plane, int x) -> frag {
@@ -406,6 +425,7 @@ hipError_t launch_dma_t(const FusedArgs &a, hipStream_t s) {
     const int64_t tiles = ((a.mi + C::TM - 1) / C::TM) * ((a.tb + C::TN - 1) / C::TN);
     if (a.mi <= 0 || a.tb <= 0) return hipSuccess;
     if ((a.n_pad * C::ESZ) % (C::KB * 64)) return hipErrorInvalidValue;
+    if (C::BF && (a.i0 % 16 || a.tcap % 16)) return hipErrorInvalidValue;   // whole fragment-ordered groups
     if constexpr (T::PERSIST) {
         if (!a.tile_counters) return hipErrorInvalidValue;
         static bool attr_set = false;   // per instantiation

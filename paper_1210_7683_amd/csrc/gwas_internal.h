@@ -102,6 +102,28 @@ __device__ __forceinline__ void bf16_split3(float x, uint16_t &hi, uint16_t &mid
     lo = bf16_rne(r - bf16_to_f32(mid));
 }
 
+// Split-BF16 planes (rotated SNPs and trait panels) are stored in MFMA
+// fragment order rather than row-major: the 1 KB block (row / 16, sample / 32),
+// at block index (row / 16) (n_pad / 32) + sample / 32, holds 16 rows x 32
+// samples in the operand lane order of the 16x16x32 BF16 MFMA: lane
+// L = ((sample mod 32) / 8) 16 + row mod 16 owns bytes 16 L .. 16 L + 15,
+// samples 8 (L / 16) .. + 7 of row L mod 16. A wave then stages a fragment with
+// one contiguous 1 KB copy (whole cache lines), where a row-major plane needs 16
+// half cache lines from 16 rows. A plane of R rows (R a multiple of 16) spans
+// R n_pad elements, as row-major.
+__host__ __device__ constexpr int64_t bf_frag_index(int64_t row, int k, int n_pad) {
+    return (((row >> 4) * (n_pad >> 5) + (k >> 5)) << 9) + ((int64_t)(((k & 31) >> 3) * 16 + (row & 15)) << 3) +
+           (k & 7);
+}
+static_assert(bf_frag_index(0, 0, 64) == 0 && bf_frag_index(1, 0, 64) == 8 && bf_frag_index(0, 8, 64) == 128 &&
+                  bf_frag_index(0, 32, 64) == 512 && bf_frag_index(16, 0, 64) == 1024 &&
+                  bf_frag_index(17, 41, 64) == 1024 + 512 + (16 + 1) * 8 + 1,
+              "fragment order");
+
+// Rows of a trait-panel plane holding t traits: a multiple of 16, so that the
+// fragment-ordered BF16 planes of consecutive contractions do not overlap.
+inline int panel_rows(int t) { return (t + 15) / 16 * 16; }
+
 // Output planes of a rotation (any pointer may be null).
 struct RotOut {
     double *f64;      // [rows][ld]
@@ -184,6 +206,10 @@ struct FusedArgs {
     int f32_flush;
     int small_t;            // nonzero: the call has at most kSmallT traits (dot-product kernel)
     unsigned *tile_counters;  // 8 device words for persistent launches (zeroed by the launcher)
+    // Rows [i0, i0 + row_lo) are computed but not stored: the split-BF16 forms
+    // stage whole 16-row groups of their fragment-ordered store, so a range
+    // starting inside a group starts at the group (b row i lands at i - row_lo).
+    int64_t row_lo;
 };
 hipError_t launch_fused(int form, const FusedArgs &a, hipStream_t s);
 

@@ -37,20 +37,21 @@ __device__ __forceinline__ void put(void *panels, int plane, int tcap, int j, in
         ((double *)panels)[o] = v;
     } else if constexpr (FORM == GWAS_FORM_F32) {
         ((float *)panels)[o] = (float)v;
-    } else if constexpr (FORM == GWAS_FORM_BF16X3) {
-        uint16_t h, l;
-        bf16_split((float)v, h, l);
-        const int64_t o2 = ((int64_t)(2 * plane) * tcap + j) * n_pad + k;
-        ((uint16_t *)panels)[o2] = h;
-        ((uint16_t *)panels)[o2 + (int64_t)tcap * n_pad] = l;
-    } else {
-        uint16_t h, md, l;
-        bf16_split3((float)v, h, md, l);
-        const int64_t o3 = ((int64_t)(3 * plane) * tcap + j) * n_pad + k;
+    } else {   // split BF16: fragment-ordered planes (tcap a multiple of 16)
         const int64_t ps = (int64_t)tcap * n_pad;
-        ((uint16_t *)panels)[o3] = h;
-        ((uint16_t *)panels)[o3 + ps] = md;
-        ((uint16_t *)panels)[o3 + 2 * ps] = l;
+        const int64_t f = bf_frag_index(j, k, n_pad);
+        if constexpr (FORM == GWAS_FORM_BF16X3) {
+            uint16_t h, l;
+            bf16_split((float)v, h, l);
+            ((uint16_t *)panels)[2 * plane * ps + f] = h;
+            ((uint16_t *)panels)[(2 * plane + 1) * ps + f] = l;
+        } else {
+            uint16_t h, md, l;
+            bf16_split3((float)v, h, md, l);
+            ((uint16_t *)panels)[3 * plane * ps + f] = h;
+            ((uint16_t *)panels)[(3 * plane + 1) * ps + f] = md;
+            ((uint16_t *)panels)[(3 * plane + 2) * ps + f] = l;
+        }
     }
 }
 

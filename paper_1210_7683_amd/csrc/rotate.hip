@@ -47,19 +47,22 @@ __device__ __forceinline__ void rot_store(const RotOut &out, int64_t i, int k, d
     const int64_t o = (out.row0 + i) * out.ld + k;
     if (out.f64) out.f64[o] = v;
     if (out.f32) out.f32[o] = (float)v;
-    if (out.bf) {
-        uint16_t h, l;
-        bf16_split((float)v, h, l);
-        out.bf[o] = h;
-        out.bf[out.plane_rows * out.ld + o] = l;
-    }
-    if (out.bf3) {
-        uint16_t h, md, l;
-        bf16_split3((float)v, h, md, l);
+    if (out.bf || out.bf3) {   // fragment-ordered planes (bf_frag_index)
+        const int64_t f = bf_frag_index(out.row0 + i, k, out.ld);
         const int64_t ps = out.plane_rows * out.ld;
-        out.bf3[o] = h;
-        out.bf3[ps + o] = md;
-        out.bf3[2 * ps + o] = l;
+        if (out.bf) {
+            uint16_t h, l;
+            bf16_split((float)v, h, l);
+            out.bf[f] = h;
+            out.bf[ps + f] = l;
+        }
+        if (out.bf3) {
+            uint16_t h, md, l;
+            bf16_split3((float)v, h, md, l);
+            out.bf3[f] = h;
+            out.bf3[ps + f] = md;
+            out.bf3[2 * ps + f] = l;
+        }
     }
 }
 

@@ -10,10 +10,11 @@ constexpr int kServeMaxItems = 32;  // work items per launch (one per admitted r
 
 // One work item: a slab of SNPs of one request against all its traits.
 struct ServeItem {
-    const void *panels;   // the request's trait panels (plane stride tcap = tb rows)
+    const void *panels;   // the request's trait panels (plane stride tcap = tb rounded up to 16 rows)
     const double *fac;    // its per-trait factors
     void *b;              // device staging for the slab's b: mi x tb x p
     int64_t i0, mi;       // SNP range
+    int64_t row_lo;       // rows [i0, i0 + row_lo) computed but not stored (FusedArgs::row_lo)
     int64_t tile0;        // first tile index of this item within the launch
     int32_t tb, p, tcap, fac_stride;
 };

@@ -52,6 +52,7 @@ __global__ __launch_bounds__((ServeCfg<FORM, FLUSH>::NT)) void serve_kernel(Serv
         fa.a_plane_rows = bt.a_plane_rows;
         fa.i0 = s.i0;
         fa.mi = s.mi;
+        fa.row_lo = s.row_lo;
         fa.panels = s.panels;
         fa.tcap = s.tcap;
         fa.fac = s.fac;

@@ -107,7 +107,7 @@ struct Copy {
 size_t panel_bytes(int form, int p, int t, int n_pad) {
     const size_t elt = form == GWAS_FORM_F64 ? 8 : (form == GWAS_FORM_F32 ? 4 : 2);
     const size_t planes = (form == GWAS_FORM_BF16X3 ? 2 : form == GWAS_FORM_BF16X6 ? 3 : 1) * (size_t)(p + 1);
-    return elt * planes * t * n_pad;
+    return elt * planes * panel_rows(t) * n_pad;
 }
 
 }  // namespace
@@ -243,8 +243,8 @@ gwas_status start_request(gwas_server *s, Req *r) {
     HIP_TRY(hipMemcpyAsync(r->d_h2, s->slot_h2[r->slot], sizeof(double) * r->t, hipMemcpyHostToDevice, s->s_comp));
     RotOut ro{r->d_yt, nullptr, nullptr, nullptr, 0, 0, c->n_pad};
     HIP_TRY(launch_rotate(r->d_y, GWAS_DT_F64, r->t, c->n, c->n, c->Z, c->n_pad, ro, s->s_comp));
-    PrepArgs pa{r->d_yt, r->d_h2, c->w, c->xlt, r->d_panels, r->d_fac, r->t, c->n, c->n_pad, r->p, r->t,
-                fac_stride(r->p), s->form};
+    PrepArgs pa{r->d_yt, r->d_h2, c->w, c->xlt, r->d_panels, r->d_fac, r->t, c->n, c->n_pad, r->p,
+                panel_rows(r->t), fac_stride(r->p), s->form};
     HIP_TRY(launch_prep(pa, s->s_comp));
     return GWAS_OK;
 }
@@ -335,12 +335,19 @@ void sched_loop(gwas_server *s) {
             it.b = r->d_stage[st];
             it.i0 = r->i0 + s0;
             it.mi = cnt;
+            it.row_lo = 0;
+            if (s->form == GWAS_FORM_BF16X3 || s->form == GWAS_FORM_BF16X6) {
+                // whole 16-row groups of the fragment-ordered store (see FusedArgs::row_lo)
+                it.row_lo = it.i0 & 15;
+                it.i0 -= it.row_lo;
+                it.mi += it.row_lo;
+            }
             it.tile0 = bt.total_tiles;
             it.tb = r->t;
             it.p = r->p;
-            it.tcap = r->t;
+            it.tcap = panel_rows(r->t);
             it.fac_stride = fac_stride(r->p);
-            bt.total_tiles += ((cnt + tm - 1) / tm) * (int64_t)((r->t + tn - 1) / tn);
+            bt.total_tiles += ((it.mi + tm - 1) / tm) * (int64_t)((r->t + tn - 1) / tn);
             Copy cp;
             cp.r = r;
             cp.stage = st;

@@ -65,7 +65,7 @@ def test_trait_factors(setup_small):
 def test_f64_panels(setup_small):
     d = setup_small
     p, n = d["p"], d["n"]
-    got = d["c"].debug_copy("panels", "f64").reshape(p + 1, 8, 128)
+    got = d["c"].debug_copy("panels", "f64").reshape(p + 1, 16, 128)   # planes of 8 traits padded to 16 rows
     xlp = d["xl"] @ d["z"]
     yp = d["y"] @ d["z"]
     for j in range(d["t"]):
@@ -74,4 +74,34 @@ def test_f64_panels(setup_small):
         for c in range(p - 1):
             assert np.allclose(got[1 + c, j, :n], dj * xlp[c], rtol=1e-12, atol=1e-13)
         assert np.allclose(got[p, j, :n], dj * yp[j], rtol=1e-12, atol=1e-13)
-    assert not got[:, :, n:].any()
+    assert not got[:, :d["t"], n:].any()
+
+
+def _unfragment(plane, rows, n_pad):
+    """A split-BF16 plane in MFMA fragment order -> [rows][n_pad]: the 1 KB block
+    (row // 16, k // 32) holds lane L = ((k % 32) // 8) * 16 + row % 16 at
+    elements 8 L .. 8 L + 7 (samples 8 ((k % 32) // 8) .. + 7 of that row)."""
+    b = plane.reshape(rows // 16, n_pad // 32, 4, 16, 8)      # [row group][k group][k quarter][row][k]
+    return b.transpose(0, 3, 1, 2, 4).reshape(rows, n_pad)
+
+
+def test_split_bf16_panels_in_fragment_order(setup_small):
+    """The two-piece form's panels (hi and lo planes per contraction) in fragment
+    order: hi + lo is the FP32 rounding of the FP64 panel value to within BF16's
+    two-piece precision, and samples beyond n are zero."""
+    d = setup_small
+    p, n = d["p"], d["n"]
+    d["c"].solve(d["y"], d["h2"], form="bf16x3")
+    raw = d["c"].debug_copy("panels", "bf16x3").reshape(2 * (p + 1), 16 * 128)
+    val = lambda u: (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    planes = np.stack([_unfragment(raw[k], 16, 128) for k in range(2 * (p + 1))])
+    xlp = d["xl"] @ d["z"]
+    yp = d["y"] @ d["z"]
+    for j in range(d["t"]):
+        dj = 1.0 / (d["h2"][j] * d["w"] + 1 - d["h2"][j])
+        refs = [dj] + [dj * xlp[c] for c in range(p - 1)] + [dj * yp[j]]
+        for q, ref in enumerate(refs):
+            got = val(planes[2 * q, j, :n]) + val(planes[2 * q + 1, j, :n])
+            assert np.abs(got - ref).max() <= 2.0 ** -16 * np.abs(ref).max(), (j, q)
+            assert not planes[2 * q : 2 * q + 2, j, n:].any()
+    d["c"].solve(d["y"], d["h2"], form="f64")   # leave the f64 panels for other tests
