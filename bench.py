@@ -368,9 +368,16 @@ def run_serving(workload, form, rate, requests, warmup_requests, slots=8, ring_s
         "mean_traits": float(np.mean([reqs[k].y.shape[0] for k in meas])),
         "d2h_gbps": bytes_b / span / 1e9, "window_s": span, "all_done": ok,
         "server": sst, "checksummed": not skip_checksum,
+        # the grouped launches: slabs per launch, and the serving kernel's own rate over
+        # every request (warm-up ones included), algorithmic 2 (p + 1) n flops per problem
+        "items_per_launch": sst["items"] / max(1, sst["rounds"]),
+        "kernel_gls_per_s": sum(r["problems"] for r in res) / max(1e-9, sst["kernel_s"]),
+        "kernel_tflops": sum(res[k]["problems"] * 2 * (reqs[k].p + 1) * w.n for k in range(len(reqs)))
+                         / max(1e-9, sst["kernel_s"]) / 1e12,
     }
-    log("serving at %.1f req/s: p50 %.3f s, p99 %.3f s, %.3e GLS/s, b to host %.1f GB/s" %
-        (rate, line["latency_p50_s"], line["latency_p99_s"], line["value"], line["d2h_gbps"]))
+    log("serving at %.1f req/s: p50 %.3f s, p99 %.3f s, %.3e GLS/s, b to host %.1f GB/s; %.2f slabs per "
+        "launch, kernel %.1f TFLOP/s" % (rate, line["latency_p50_s"], line["latency_p99_s"], line["value"],
+                                        line["d2h_gbps"], line["items_per_launch"], line["kernel_tflops"]))
     return line
 
 
@@ -552,7 +559,8 @@ def main():
         line["serving"] = {"workload": "serve_m1e6", "form": "f32", "rate_hz": args.rate,
                            "requests": s["config"]["requests"], "latency_p50_s": s["latency_p50_s"],
                            "latency_p99_s": s["latency_p99_s"], "gls_per_s": s["value"],
-                           "d2h_gbps": s["d2h_gbps"], "all_done": s["all_done"]}
+                           "d2h_gbps": s["d2h_gbps"], "all_done": s["all_done"],
+                           "items_per_launch": s["items_per_launch"], "kernel_tflops": s["kernel_tflops"]}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         line["cpu_baseline"] = cpu_baseline(w, phi, xl)

@@ -319,12 +319,14 @@ const char *gwas_last_error(void);
  *
  * A server owns a scheduler thread and a consumer thread. Submitted requests
  * wait in FIFO order until a slot is free and their device memory (rotated
- * traits, panels, factors, three b staging buffers) fits in the server's HBM
+ * traits, panels, factors, four b staging buffers) fits in the server's HBM
  * budget; they are then admitted, their traits rotated and prepared, and
  * their SNP range is cut into work items (slabs). Every scheduling round
- * takes the next slab of each admitted request and runs all of them in one
- * launch, whatever their trait count and covariate count; requests that
- * arrive meanwhile join the next round. Each slab's b is copied to the host
+ * takes each admitted request's slabs that can start (a free staging buffer
+ * and, for ring output, a free ring slot) and runs all of them in one launch,
+ * whatever their trait count and covariate count; a round is built when the
+ * previous round's kernel has finished, so slabs that become ready meanwhile,
+ * and requests that arrive meanwhile, join the next round. Each slab's b is copied to the host
  * on a second stream: into the request's own buffer when it gave one, else
  * through a ring of pinned host slots where a worker thread checksums it (the
  * checksum of gwas_solve_stream) and passes it to the request's callback, if
@@ -346,8 +348,9 @@ typedef struct gwas_server_options {
     int32_t ring_slots;  /* pinned host ring slots; 0: 2 x max_slots                       */
     int32_t host_threads;/* checksum worker threads (one ring slab each at a time); 0: 8    */
     int32_t skip_checksum; /* nonzero: ring slabs are handed to the callback unchecksummed */
-    int32_t grid_wgs;    /* persistent workgroups per launch; 0: two per compute unit
-                            (measured best; the copy kernels still get their share)      */
+    int32_t grid_wgs;    /* persistent workgroups per launch; 0: as many as fit a compute unit
+                            at once, at most two per unit (the copy kernels still get
+                            their share)                                                  */
     int32_t reserved[4];
 } gwas_server_options;
 

@@ -33,6 +33,9 @@ struct ServeBatch {
 // Tile shape (SNPs x traits per tile) of the serving kernel for a form and p.
 void serve_tile_shape(int form, bool flush, int p, int &tm, int &tn);
 
+// Workgroups of the serving kernel that fit one CU at once (LDS, registers).
+int serve_occupancy(int form, bool flush);
+
 // Launch `grid` persistent workgroups over the batch's tiles.
 hipError_t launch_serve(int form, bool flush, const ServeBatch &bt, int grid, hipStream_t s);
 

@@ -14,14 +14,17 @@ namespace gw {
 namespace {
 
 // Tile code of the direct solve (fused_dma.h) with one workgroup shape for all
-// p of a launch: 4 waves of one 16x16 block each, 64 SNPs x 16 traits per tile
-// (requests have few traits, so narrow trait tiles waste little).
+// p of a launch: the direct solve's tiles for p = 5..9 (8 waves; FP64 64 SNPs x
+// 32 traits, FP32 128 x 16, split BF16 256 x 16, three-piece 128 x 16).
+// Requests have few traits, so narrow trait tiles waste little; a problem's
+// sums take the same MFMAs in the same order as in every direct-solve kernel.
 // The three-piece split BF16 form always folds its FP32 sums into FP64 per stage.
 template <int FORM, bool FLUSH>
 struct ServeTile {
-    using type = typename std::conditional<FORM == GWAS_FORM_F64, DmaTile<4, 1, 1, 1, 1>,
-                 typename std::conditional<FORM == GWAS_FORM_F32, DmaTile<4, 1, 1, 1, 2, true>,
-                                           DmaTile<4, 1, 1, 1, 1, true>>::type>::type;
+    using type = typename std::conditional<FORM == GWAS_FORM_F64, DmaTile<4, 2, 1, 1, 1>,
+                 typename std::conditional<FORM == GWAS_FORM_F32, DmaTile<8, 1, 1, 1, 2, true>,
+                 typename std::conditional<FORM == GWAS_FORM_BF16X3, DmaTile<8, 1, 2, 1, 1, true>,
+                                           DmaTile<8, 1, 1, 1, 1, true>>::type>::type>::type;
     static_assert(FORM != GWAS_FORM_BF16X6 || FLUSH, "the three-piece form folds every stage");
 };
 
@@ -93,6 +96,20 @@ hipError_t launch_serve_t(const ServeBatch &bt, int grid, hipStream_t s) {
 }
 
 template <int FORM, bool FLUSH>
+int occupancy_t() {
+    using SC = ServeCfg<FORM, FLUSH>;
+    if (SC::LDS > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)serve_kernel<FORM, FLUSH>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, SC::LDS);
+        if (e != hipSuccess) return 1;
+    }
+    int n = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, serve_kernel<FORM, FLUSH>, SC::NT, SC::LDS) != hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+
+template <int FORM, bool FLUSH>
 void tile_shape_t(int p, int &tm, int &tn) {
     using T = typename ServeTile<FORM, FLUSH>::type;
     switch (p) {
@@ -111,6 +128,14 @@ void serve_tile_shape(int form, bool flush, int p, int &tm, int &tn) {
     else if (form == GWAS_FORM_F32 && flush) tile_shape_t<GWAS_FORM_F32, true>(p, tm, tn);
     else if (form == GWAS_FORM_F32) tile_shape_t<GWAS_FORM_F32, false>(p, tm, tn);
     else tile_shape_t<GWAS_FORM_BF16X3, false>(p, tm, tn);
+}
+
+int serve_occupancy(int form, bool flush) {
+    if (form == GWAS_FORM_F64) return occupancy_t<GWAS_FORM_F64, false>();
+    if (form == GWAS_FORM_BF16X6) return occupancy_t<GWAS_FORM_BF16X6, true>();
+    if (form == GWAS_FORM_F32 && flush) return occupancy_t<GWAS_FORM_F32, true>();
+    if (form == GWAS_FORM_F32) return occupancy_t<GWAS_FORM_F32, false>();
+    return occupancy_t<GWAS_FORM_BF16X3, false>();
 }
 
 hipError_t launch_serve(int form, bool flush, const ServeBatch &bt, int grid, hipStream_t s) {

@@ -64,9 +64,15 @@ def test_alone_equals_mix_and_matches_oracle(cohort_all, form):
     reqs = _requests(1, 7)
     with gwas.Server(d["c"], form=form, max_slots=4, item_problems=6000, max_traits=64) as srv:
         alone, _ = _run(srv, reqs, together=False)
+        st0 = srv.stats()
         mix, res = _run(srv, reqs, together=True)
+        st1 = srv.stats()
     for a, b in zip(alone, mix):
         assert np.array_equal(a, b)
+    # the mix was batched: its grouped launches carried more than one slab each on average
+    items, rounds = st1["items"] - st0["items"], st1["rounds"] - st0["rounds"]
+    print("%s mix: %d slabs in %d launches" % (form, items, rounds))
+    assert items > rounds
     # overlap: in the mix, some request was admitted before another finished
     spans = sorted((r["t_admit"], r["t_done"]) for r in res)
     assert any(spans[k + 1][0] < spans[k][1] for k in range(len(spans) - 1))
@@ -159,7 +165,7 @@ def test_admission_by_memory_serialises_requests(cohort_all):
     d = cohort_all
     rng = np.random.default_rng(3)
     reqs = [(rng.standard_normal((64, N)), rng.uniform(0.1, 0.9, 64), 4) for _ in range(4)]
-    # each request holds ~1.1 MB (traits, panels, factors, three 256 KB b stages):
+    # each request holds ~1.4 MB (traits, panels, factors, four 256 KB b stages):
     # a 1.6 MB budget admits one at a time although 8 slots are free
     with gwas.Server(d["c"], form="f32", max_slots=8, hbm_budget=1600 << 10, item_problems=6000,
                      max_traits=64) as srv:
