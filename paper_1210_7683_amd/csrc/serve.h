@@ -22,7 +22,11 @@ struct ServeItem {
 struct ServeBatch {
     const void *a;               // resident rotated SNPs of the form
     int64_t a_plane_rows;
-    unsigned int *counter;       // tile counter, zero at launch
+    // Tile counter, never reset: every workgroup takes tiles with an atomic add
+    // until it draws one past the round's list, so one round advances it by
+    // exactly total_tiles + grid, and the next round's tiles start there.
+    unsigned long long *counter;
+    unsigned long long counter_base;   // the counter's value when this round starts
     unsigned long long *non_spd;
     int64_t total_tiles;
     double rank_rtol;

@@ -40,11 +40,11 @@ template <int FORM, bool FLUSH>
 __global__ __launch_bounds__((ServeCfg<FORM, FLUSH>::NT)) void serve_kernel(ServeBatch bt) {
     using T = typename ServeTile<FORM, FLUSH>::type;
     extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
-    __shared__ unsigned int next;
+    __shared__ unsigned long long next;
     for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(bt.counter, 1u);
+        if (threadIdx.x == 0) next = atomicAdd(bt.counter, 1ull);
         __syncthreads();
-        const int64_t tile = next;
+        const int64_t tile = (int64_t)(next - bt.counter_base);
         __syncthreads();   // every thread has read `next` before it is overwritten
         if (tile >= bt.total_tiles) return;
         int it = 0;

@@ -130,7 +130,8 @@ struct gwas_server {
 
     Arena arena;
     void *arena_mem = nullptr;
-    unsigned int *d_counter = nullptr;
+    unsigned long long *d_counter = nullptr;
+    uint64_t counter_next = 0;   // the tile counter's value when the next round starts
     hipStream_t s_comp = nullptr, s_copy = nullptr;
     std::vector<void *> ring;
     std::vector<void *> ring_dev;   // device-side addresses of the ring slots
@@ -321,6 +322,7 @@ void sched_loop(gwas_server *s) {
         bt.a = a_base;
         bt.a_plane_rows = c->m_rows;
         bt.counter = s->d_counter;
+        bt.counter_base = s->counter_next;
         bt.non_spd = c->counters;
         bt.rank_rtol = kRankRtol[s->form];
         bt.n_pad = c->n_pad;
@@ -403,7 +405,7 @@ void sched_loop(gwas_server *s) {
         hipEvent_t ev_round = pool_get(s);
         lk.unlock();
         const double t_issue = now_s();
-        hipError_t e = ev_round ? hipMemsetAsync(s->d_counter, 0, sizeof(unsigned int), s->s_comp) : hipErrorOutOfMemory;
+        hipError_t e = ev_round ? hipSuccess : hipErrorOutOfMemory;
         if (e == hipSuccess && round[0].ev_kbeg) e = hipEventRecord(round[0].ev_kbeg, s->s_comp);
         if (e == hipSuccess) e = launch_serve(s->form, s->flush, bt, s->grid, s->s_comp);
         if (e == hipSuccess && round[0].ev_kend) e = hipEventRecord(round[0].ev_kend, s->s_comp);
@@ -444,6 +446,8 @@ void sched_loop(gwas_server *s) {
             continue;
         }
         s->rounds.push_back(ev_round);
+        if (bt.total_tiles > 0 && s->grid > 0)   // launch_serve launched the kernel
+            s->counter_next += (uint64_t)bt.total_tiles + (uint64_t)s->grid;
         for (Copy &cp : round) {
             s->bytes_d2h += cp.info.bytes;
             s->copies.push_back(cp);
@@ -603,6 +607,7 @@ gwas_status gwas_server_create(gwas_ctx *c, const gwas_server_options *opt, gwas
     s->grid = opt->grid_wgs > 0 ? opt->grid_wgs : std::min(2, serve_occupancy(s->form, s->flush)) * cus;
     if (e == hipSuccess) e = hipMalloc(&s->arena_mem, budget);
     if (e == hipSuccess) e = hipMalloc((void **)&s->d_counter, 256);
+    if (e == hipSuccess) e = hipMemset(s->d_counter, 0, 256);
     // The copy stream must not share a hardware queue with the compute stream, or
     // the copies (blit kernels) wait behind every launch: streams created with a
     // compute-unit mask (here: all units) get hardware queues of their own.
