@@ -429,6 +429,7 @@ FusedArgs fused_args(gwas_ctx *c, const TraitScratch &ts, int jb, int32_t form, 
     fa.fac_stride = fac_stride(c->p);
     fa.tb = jb;
     fa.n_pad = c->n_pad;
+    fa.n = c->n;
     fa.p = c->p;
     fa.rank_rtol = kRankRtol[form];
     fa.non_spd = c->counters;

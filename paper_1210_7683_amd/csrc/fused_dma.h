@@ -122,7 +122,8 @@ __device__ __forceinline__ void dma_tile(const FusedArgs &a, int64_t tile, uint8
     const int l16 = lane & 15, g = lane >> 4;
 
     const int64_t row_bytes = (int64_t)a.n_pad * C::ESZ;
-    const int nstages = (int)(row_bytes / (KB * 64));
+    // stages up to the one holding sample n - 1 (the rest of the row is zeros)
+    const int nstages = (int)(((int64_t)a.n * C::ESZ + KB * 64 - 1) / (KB * 64));
     const uint8_t *A = (const uint8_t *)a.a;
     const uint8_t *B = (const uint8_t *)a.panels;
     const int64_t a_plane = a.a_plane_rows * row_bytes;

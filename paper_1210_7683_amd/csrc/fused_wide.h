@@ -63,7 +63,9 @@ __device__ __forceinline__ void wide_tile(const FusedArgs &a, int64_t m_base, in
     const int l16 = lane & 15, g = lane >> 4;
 
     const int nkg = a.n_pad / 32;                             // 32-sample groups per row
-    const int nstages = nkg;                                  // one group per stage; even (n_pad % 64 == 0)
+    // one group per stage, up to the pair holding sample n - 1 (the rest of
+    // the row is zeros); even, at most nkg (n_pad % 64 == 0)
+    const int nstages = 2 * ((a.n + 63) / 64);
     const int64_t a_plane = a.a_plane_rows * (int64_t)a.n_pad * 2;
     const int64_t b_plane = (int64_t)a.tcap * a.n_pad * 2;
     const int64_t g0 = (a.i0 + m_base) / 16, g_last = (a.i0 + a.mi - 1) / 16;

@@ -199,6 +199,8 @@ struct FusedArgs {
     int fac_stride;
     int tb;                 // traits in this sub-block
     int n_pad, p;
+    int n;                  // samples: both operands are zero from n to n_pad, so a
+                            // K loop may stop at the stage that holds sample n - 1
     void *b;                // output: b[(i - i0) * ldt + j] * p ...
     int64_t ldt;            // trait stride of b (in problems)
     double rank_rtol;

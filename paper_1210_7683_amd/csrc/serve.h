@@ -30,7 +30,7 @@ struct ServeBatch {
     unsigned long long *non_spd;
     int64_t total_tiles;
     double rank_rtol;
-    int32_t n_pad, f32_flush, n_items, pad_;
+    int32_t n_pad, f32_flush, n_items, n;   // n: samples (zeros from n to n_pad)
     ServeItem items[kServeMaxItems];
 };
 

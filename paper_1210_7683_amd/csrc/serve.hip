@@ -62,6 +62,7 @@ __global__ __launch_bounds__((ServeCfg<FORM, FLUSH>::NT)) void serve_kernel(Serv
         fa.fac_stride = s.fac_stride;
         fa.tb = s.tb;
         fa.n_pad = bt.n_pad;
+        fa.n = bt.n;
         fa.p = s.p;
         fa.b = s.b;
         fa.ldt = s.tb;

@@ -326,6 +326,7 @@ void sched_loop(gwas_server *s) {
         bt.non_spd = c->counters;
         bt.rank_rtol = kRankRtol[s->form];
         bt.n_pad = c->n_pad;
+        bt.n = c->n;
         bt.f32_flush = s->flush ? c->f32_flush : 0;
         const int na = (int)s->active.size();
         for (int k = 0; k < na && bt.n_items < kServeMaxItems; ++k) {
