@@ -12,6 +12,7 @@
 #include <mutex>
 #include <unordered_map>
 
+#include "arena.h"
 #include "ctx.h"
 #include "serve.h"
 
@@ -37,48 +38,6 @@ constexpr int kCopyGrid = 64;
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
-
-// First-fit sub-allocator over one device allocation (256-byte granules).
-struct Arena {
-    uint8_t *base = nullptr;
-    size_t size = 0;
-    std::map<size_t, size_t> free_;   // offset -> bytes, coalesced
-
-    void init(void *p, size_t bytes) {
-        base = (uint8_t *)p;
-        size = bytes;
-        free_.clear();
-        free_[0] = bytes;
-    }
-    bool alloc(size_t bytes, size_t *off) {
-        bytes = (size_t)round_up((int64_t)bytes, 256);
-        for (auto it = free_.begin(); it != free_.end(); ++it)
-            if (it->second >= bytes) {
-                *off = it->first;
-                const size_t rest = it->second - bytes, o2 = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[o2] = rest;
-                return true;
-            }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        bytes = (size_t)round_up((int64_t)bytes, 256);
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-};
 
 struct Req {
     uint64_t ticket = 0;
