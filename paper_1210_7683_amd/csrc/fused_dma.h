@@ -461,7 +461,11 @@ hipError_t launch_dma_t(const FusedArgs &a, hipStream_t s) {
 
 // Per-form tiles, chosen by timing sweeps on the MI355X at n = 1000, p = 4
 // (m = 1e5, t = 1000): one 16x16 block of problems per wave for FP64 and FP32,
-// 32x32 per wave for split BF16 (more reuse of its larger operands). FP32 and
+// 32x32 per wave for split BF16 (more reuse of its larger operands). FP64 at
+// m = 1e6: 8 waves in a column (128 SNPs x 16 traits) took 143.0-143.5 ms
+// against 145.3-146.2 ms for 4 x 2 waves (64 x 32), 144.1-144.5 ms for 4 x 2
+// waves of 32 x 16 blocks and 143.1 ms for 8 waves of 32 x 16 blocks; it is
+// also 2.6% faster at p = 8 but 1.3% slower at p = 2, which keeps 4 x 2. FP32 and
 // split BF16 run two LDS buffers (PIPE); for FP64 the single buffer with a
 // smaller LDS footprint measured faster. Persistent workgroups measured 2-6%
 // faster than one workgroup per tile for split BF16 at p <= 4 (varying
@@ -470,7 +474,8 @@ hipError_t launch_dma_t(const FusedArgs &a, hipStream_t s) {
 // a wave may hold up to 512 registers of p + 1 accumulator sets and fragments.
 template <int FORM, int P>
 struct DmaDefault {
-    using F64T = typename std::conditional<(P <= 9), DmaTile<4, 2, 1, 1, 1>, DmaTile<4, 1, 1, 1, 1>>::type;
+    using F64T = typename std::conditional<(P == 2), DmaTile<4, 2, 1, 1, 1>,
+                 typename std::conditional<(P <= 9), DmaTile<8, 1, 1, 1, 1>, DmaTile<4, 1, 1, 1, 1>>::type>::type;
     using F32T = typename std::conditional<(P <= 11), DmaTile<8, 1, 1, 1, 2, true>,
                                            DmaTile<4, 1, 1, 1, 2, true>>::type;
     using BF16T = typename std::conditional<(P <= 4), DmaTile<8, 1, 2, 2, 1, true, true>,

@@ -14,14 +14,14 @@ namespace gw {
 namespace {
 
 // Tile code of the direct solve (fused_dma.h) with one workgroup shape for all
-// p of a launch: the direct solve's tiles for p = 5..9 (8 waves; FP64 64 SNPs x
-// 32 traits, FP32 128 x 16, split BF16 256 x 16, three-piece 128 x 16).
+// p of a launch: the direct solve's tiles for p = 5..9 (8 waves; FP64 and FP32
+// 128 SNPs x 16 traits, split BF16 256 x 16, three-piece 128 x 16).
 // Requests have few traits, so narrow trait tiles waste little; a problem's
 // sums take the same MFMAs in the same order as in every direct-solve kernel.
 // The three-piece split BF16 form always folds its FP32 sums into FP64 per stage.
 template <int FORM, bool FLUSH>
 struct ServeTile {
-    using type = typename std::conditional<FORM == GWAS_FORM_F64, DmaTile<4, 2, 1, 1, 1>,
+    using type = typename std::conditional<FORM == GWAS_FORM_F64, DmaTile<8, 1, 1, 1, 1>,
                  typename std::conditional<FORM == GWAS_FORM_F32, DmaTile<8, 1, 1, 1, 2, true>,
                  typename std::conditional<FORM == GWAS_FORM_BF16X3, DmaTile<8, 1, 2, 1, 1, true>,
                                            DmaTile<8, 1, 1, 1, 1, true>>::type>::type>::type;
