@@ -83,7 +83,11 @@ typedef struct gwas_options {
                             events on its stream (read back by gwas_stats)           */
     int32_t ring_slots;  /* gwas_solve_stream: pinned host slots of the b ring; 0: 4  */
     int32_t host_threads;/* gwas_solve_stream: threads per slab checksum; 0: 8        */
-    int32_t reserved[6];
+    int32_t geno_chunk_snps; /* genotype (GWAS_DT_U8) rotation: SNPs per chunk repacked
+                            on the device before the int8 kernels, a multiple of 256;
+                            the context holds a buffer of this many rows of n rounded
+                            up to 64 bytes; 0: the rows that fit 256 MiB (at least 256) */
+    int32_t reserved[5];
 } gwas_options;
 
 typedef struct gwas_stats_t {
@@ -156,7 +160,9 @@ gwas_status gwas_setup(gwas_ctx **ctx, int32_t n, int32_t p, const double *Z, co
  * FP64: six digits (47 bits per eigenvector, relative to its largest entry;
  * about 3e-14 of the row's maximum from the FP64 GEMM) when the context keeps
  * the FP64 form, else the leading four (about 4e-8 of the row's maximum, at
- * the FP32 rounding of the stored values).
+ * the FP32 rounding of the stored values). The genotype rows are repacked on
+ * the device, geno_chunk_snps at a time, into the context's buffer in the
+ * MFMA operand order; any row length, stride and alignment is accepted.
  *   X_R        n x mb, SNP-major, element type dtype (GWAS_DT_*)
  *   on_device  nonzero: X_R is device memory; zero: host memory (copied in
  *              bounded chunks through a device staging buffer)

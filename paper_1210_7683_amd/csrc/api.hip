@@ -90,7 +90,7 @@ void release(gwas_ctx *c) {
         }
     void *ptrs[] = {c->Z, c->w, c->xlt, c->xr64, c->xr32, c->xrbf, c->y_in, c->yt, c->h2,
                     c->panels[0], c->panels[1], c->panels[2], c->panels[3], c->xrbf3, c->fac, c->counters, c->stage,
-                    c->bstage[0], c->bstage[1], c->xin[0], c->xin[1], c->zq, c->zoff, c->zscale};
+                    c->bstage[0], c->bstage[1], c->xin[0], c->xin[1], c->zq, c->zoff, c->zscale, c->zpack};
     for (void *p : ptrs)
         if (p) hipFree(p);
     for (int i = 0; i < 2; ++i) {
@@ -202,6 +202,8 @@ gwas_status gwas_setup(gwas_ctx **out, int32_t n, int32_t p, const double *Z, co
     if (opt->max_traits < 0 || opt->slab_snps < 0 || opt->f32_flush < 0 || opt->ring_slots < 0 ||
         opt->host_threads < 0 || opt->ring_slots > 64 || opt->host_threads > 256)
         return fail(GWAS_EINVAL, "negative option");
+    if (opt->geno_chunk_snps < 0 || opt->geno_chunk_snps % 256)
+        return fail(GWAS_EINVAL, "geno_chunk_snps = %d: a non-negative multiple of 256", opt->geno_chunk_snps);
     if (opt->f32_flush != 0 && opt->f32_flush != 2)
         return fail(GWAS_EINVAL, "f32_flush = %d: 0 (no fold) or 2 (FP64 folds, the default)", opt->f32_flush);
     const uint32_t forms = opt->forms ? opt->forms : 7u;
@@ -242,6 +244,9 @@ gwas_status gwas_setup(gwas_ctx **out, int32_t n, int32_t p, const double *Z, co
         TRY(dalloc(c, &c->zq, (size_t)kZSlices * np * np));
         TRY(dalloc(c, &c->zoff, sizeof(double) * 2 * np));
         TRY(dalloc(c, &c->zscale, sizeof(double) * np));
+        c->zpack_rows = opt->geno_chunk_snps ? opt->geno_chunk_snps
+                                             : std::max<int64_t>(256, kGenoPackBytes / np / 256 * 256);
+        TRY(dalloc(c, &c->zpack, (size_t)c->zpack_rows * np));
     }
     TRY(dalloc(c, &c->w, sizeof(double) * np));
     TRY(dalloc(c, &c->xlt, sizeof(double) * (size_t)(p - 1) * np));

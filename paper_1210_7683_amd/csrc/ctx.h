@@ -89,6 +89,8 @@ struct gwas_ctx {
     double *Z = nullptr;     // [n_pad][n_pad]: row k = eigenvector k (zeros beyond n)
     int8_t *zq = nullptr;    // int8 digits of Z for the genotype rotation (ZSlices)
     double *zoff = nullptr, *zscale = nullptr;   // [2][n_pad] and [n_pad]
+    uint8_t *zpack = nullptr;   // genotype repack chunk: zpack_rows x n_pad bytes
+    int64_t zpack_rows = 0;
     double *w = nullptr;     // [n_pad]
     double *xlt = nullptr;   // [p-1][n_pad]
     double *xr64 = nullptr;  // [m_rows][n_pad]
@@ -127,7 +129,7 @@ struct gwas_ctx {
     size_t ring_bytes = 0;
     std::vector<hipEvent_t> ring_ev;
 
-    gw::ZSlices zs() const { return gw::ZSlices{zq, zoff, zscale}; }
+    gw::ZSlices zs() const { return gw::ZSlices{zq, zoff, zscale, zpack, zpack_rows}; }
 
     int64_t snps_rotated = 0, problems = 0, bytes_h2d = 0, bytes_d2h = 0, resident = 0, dot_launches = 0;
 

@@ -159,13 +159,19 @@ struct ZSlices {
     const int8_t *q;       // kZSlices n_pad^2 bytes in fragment order
     const double *off;     // [2][n_pad]: 128 sum_r q_k[r], then 128 sum_r q'_k[r]
     const double *scale;   // [n_pad]: 2^-E_k (0 for an all-zero row)
+    uint8_t *pack;         // device scratch: pack_rows genotype rows of n_pad bytes in fragment
+    int64_t pack_rows;     // blocks (a multiple of 256); the rotation runs in chunks of this many rows
 };
+// Default bytes of the genotype repack chunk (rows of n_pad bytes).
+constexpr int64_t kGenoPackBytes = 256ll << 20;
 // Host: slices of the padded row-major Z (row k = eigenvector k, zeros past n).
 void slice_z_int8(const double *zh, int n_pad, int8_t *q, double *off, double *scale);
 
 // out[row0 + i][k] = sum_r X[i][r] Z[k][r]  for i < rows, k < n_pad. Genotype
-// bytes (GWAS_DT_U8) use the int8 digit kernels and need zs (n_pad <=
-// kZSliceMaxNpad; hipErrorInvalidValue otherwise); FP64 and FP32 inputs FP64 MFMA.
+// bytes (GWAS_DT_U8) use the int8 digit kernels and need zs with its pack
+// buffer (n_pad <= kZSliceMaxNpad; hipErrorInvalidValue otherwise); calls that
+// share a zs must be ordered (one stream, or events), as they share its pack
+// buffer. FP64 and FP32 inputs FP64 MFMA.
 hipError_t launch_rotate(const void *X, int dtype, int64_t rows, int n, int64_t ldx,
                          const double *Zrows, int n_pad, const RotOut &out, hipStream_t s,
                          const ZSlices *zs = nullptr);

@@ -163,216 +163,58 @@ __global__ __launch_bounds__(R::NT) void rotate_kernel(const Tin *__restrict__ X
 
 
 // Genotype rotation on the int8 MFMAs (v_mfma_i32_16x16x64_i8) with Z sliced
-// into int8 digits (ZSlices). A stage covers KS k-steps of 64 samples. In
-// k-step ks, lane group g of a wave holds samples 16 g .. 16 g + 15 of each of
-// its SNP rows (16 genotype bytes straight from global memory, prefetched a
-// stage ahead, offset by -128 to signed bytes), and Z block (ks, d, cb) in LDS
-// holds for lane l the same 16 samples of digit d of row k0 + 16 cb + l % 16,
-// so both operands put sample s in the same MFMA slot. One MFMA per (digit,
-// SNP block, Z block) and k-step; the digit sums are exact int32, recombined
-// in FP64 by the epilogue. The next stage's Z blocks and genotypes load under
-// the MFMAs; k-steps at or past n_pad (the tail of the last stage) are skipped.
-template <int WM_, int WN_, int FM_, int FN_, int KS_ = 1, int ND_ = kZSlices>
-struct RotI8 {
-    static constexpr int WM = WM_, WN = WN_, FM = FM_, FN = FN_, KS = KS_, ND = ND_;   // ND leading digits
-    static constexpr int NW = WM * WN, NT = 64 * NW;
-    static constexpr int TM = WM * FM * 16, TN = WN * FN * 16;
-    static constexpr int CB = TN / 16;                  // 16-row Z blocks of the tile
-    static constexpr int ZK = ND * CB;                  // Z blocks of one k-step, digit-major
-    static constexpr int ZB = KS * ZK;                  // Z blocks per stage
-    static constexpr int LDS = 2 * ZB * 1024;
-    static constexpr int LPW = (ZB + NW - 1) / NW;      // Z block loads per wave and stage
-    static constexpr int NF = ND * FN;                  // fragments a wave reads per k-step, (digit, y)
-    static constexpr bool frag_is_b(int) { return false; }
-    static constexpr int frag_off(int i) { return ((i / FN) * CB + i % FN) * 1024; }   // from the wave's first block
-    static_assert(ZK * 1024 <= 65536 && LDS <= 160 * 1024, "rotation stage too large");
-};
-
-template <int ND>
-using DefaultRotI8 = RotI8<4, 2, 2, 1, 1, ND>;
-
-template <class R>
-__global__ __launch_bounds__(R::NT) void rotate_u8_i8_kernel(const uint8_t *__restrict__ X, int64_t rows, int n,
-                                                             int64_t ldx, ZSlices zs, int n_pad, RotOut out) {
-    constexpr int TN = R::TN, FM = R::FM, FN = R::FN, ND = R::ND, CB = R::CB, KS = R::KS;
-    extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
-    const int ntn = n_pad / TN;
-    const int64_t tile = tile_order(blockIdx.x, (rows + R::TM - 1) / R::TM, ntn);
-    const int tn = (int)(tile % ntn);
-    const int64_t tm = tile / ntn;
-    const int64_t i_base = tm * R::TM;
-    const int k_base = tn * TN;
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wm = wave % R::WM, wn = wave / R::WM;
-    const int l16 = lane & 15, g = lane >> 4;
-    const int nk = (n + 63) / 64;                 // k-steps; 64 nk <= n_pad
-    const int nst = (nk + KS - 1) / KS;           // stages
-
-    // Z block loads of this wave: block b = ks * ZK + d * CB + cb (k-step ks,
-    // digit d, 16-row block cb)
-    const int8_t *zsrc[R::LPW];
-    int zks[R::LPW];
-#pragma unroll
-    for (int u = 0; u < R::LPW; ++u) {
-        const int b = wave + u * R::NW;
-        zsrc[u] = zs.q;
-        zks[u] = 0;
-        if (b < R::ZB) {
-            const int ks = b / R::ZK, d = (b % R::ZK) / CB, cb = b % CB;
-            zks[u] = ks;
-            zsrc[u] = zs.q + (((int64_t)d * (n_pad / 16) + k_base / 16 + cb) * (n_pad / 64) + ks) * 1024 + 16 * lane;
-        }
-    }
-    auto issue = [&](int c) {
-        uint8_t *buf = lds + (c & 1) * (R::ZB * 1024);
-#pragma unroll
-        for (int u = 0; u < R::LPW; ++u) {
-            const int b = wave + u * R::NW;
-            if (b < R::ZB && c * KS + zks[u] < nk)
-                lds_dma16((const uint8_t *)(zsrc[u] + (int64_t)c * (1024 * KS)), buf + b * 1024);
-        }
-    };
-    // genotype bytes of the wave's rows, samples 64 (c KS + ks) + 16 g .. + 15
-    // (zero past n or rows)
-    int64_t xrow[FM];
-#pragma unroll
-    for (int x = 0; x < FM; ++x) xrow[x] = i_base + wm * FM * 16 + x * 16 + l16;
-    const bool vec8 = (ldx % 8) == 0 && (((uintptr_t)X) % 8) == 0;
-    auto gload = [&](int c, uint4 (*v)[FM]) {
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const int s0 = (c * KS + ks) * 64 + 16 * g;
-#pragma unroll
-            for (int x = 0; x < FM; ++x) {
-                const int64_t i = xrow[x];
-                const uint8_t *p = X + i * ldx + s0;
-                if (vec8 && i < rows && s0 + 16 <= n) {
-                    const uint2 lo = *(const uint2 *)p, hi = *(const uint2 *)(p + 8);
-                    v[ks][x] = make_uint4(lo.x, lo.y, hi.x, hi.y);
-                } else {
-                    uint32_t w[4] = {0, 0, 0, 0};
-                    if (i < rows)
-                        for (int e = 0; e < 16; ++e)
-                            if (s0 + e < n) w[e >> 2] |= (uint32_t)p[e] << (8 * (e & 3));
-                    v[ks][x] = make_uint4(w[0], w[1], w[2], w[3]);
-                }
-            }
-        }
-    };
-
-    i4v acc[ND][FM][FN];
-#pragma unroll
-    for (int d = 0; d < ND; ++d)
-#pragma unroll
-        for (int x = 0; x < FM; ++x)
-#pragma unroll
-            for (int y = 0; y < FN; ++y) acc[d][x][y] = i4v{0, 0, 0, 0};
-
-    uint4 xa[KS][FM], xn[KS][FM];
-    issue(0);
-    gload(0, xa);
-    const uint32_t zb0 = lds_addr(lds) + lane * 16 + wn * FN * 1024;
-    for (int c = 0; c < nst; ++c) {
-        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): stage c's Z blocks and genotypes are in
-        __syncthreads();                      // every wave's too; every wave has read stage c - 1
-        const bool more = c + 1 < nst;
-        if (more) {
-            issue(c + 1);
-            gload(c + 1, xn);
-        }
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            if (c * KS + ks >= nk) break;   // the tail of the last stage (wave-uniform)
-            i4v zf[R::NF];
-            lds_read_frags<R, 0, R::NF>(zf, zb0 + (c & 1) * (R::ZB * 1024) + ks * (R::ZK * 1024), 0);
-            i4v av[FM];
-#pragma unroll
-            for (int x = 0; x < FM; ++x)   // byte v -> signed v - 128
-                av[x] = i4v{(int)(xa[ks][x].x ^ 0x80808080u), (int)(xa[ks][x].y ^ 0x80808080u),
-                            (int)(xa[ks][x].z ^ 0x80808080u), (int)(xa[ks][x].w ^ 0x80808080u)};
-#pragma unroll
-            for (int d = 0; d < ND; ++d)
-#pragma unroll
-                for (int y = 0; y < FN; ++y)
-#pragma unroll
-                    for (int x = 0; x < FM; ++x)
-                        acc[d][x][y] =
-                            __builtin_amdgcn_mfma_i32_16x16x64_i8(av[x], zf[d * FN + y], acc[d][x][y], 0, 0, 0);
-        }
-        if (more) {
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-                for (int x = 0; x < FM; ++x) xa[ks][x] = xn[ks][x];
-        }
-    }
-
-#pragma unroll
-    for (int y = 0; y < FN; ++y) {
-        const int k = k_base + wn * FN * 16 + y * 16 + l16;
-        // ND leading digits: the offset of their sum, and 2^-E_k times 256^(kZSlices - ND)
-        const double off = zs.off[(ND == kZSlices ? 0 : n_pad) + k];
-        const double sc = zs.scale[k] * (double)(1ull << (8 * (kZSlices - ND)));
-#pragma unroll
-        for (int x = 0; x < FM; ++x)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t i = i_base + wm * FM * 16 + x * 16 + mfma16_row<false>(g, r);
-                double v = (double)acc[0][x][y][r];
-#pragma unroll
-                for (int d = 1; d < ND; ++d) v = fma(v, 256.0, (double)acc[d][x][y][r]);
-                if (i < rows) rot_store(out, i, k, (v + off) * sc);
-            }
-    }
-}
-
-// The same rotation with the genotypes staged through LDS as well, for
-// genotype rows whose stride, base address and length n are multiples of 4
-// bytes: both operands are loaded by direct global->LDS copies into a ring of
-// three stage buffers, two stages ahead of the MFMAs, and each wave waits only
-// for the stage it is about to read (every wave issues the same number of
-// copies per stage). A genotype block is a 1 KB fragment block filled by
-// copies of 4 bytes per lane (16 rows x 16 bytes per instruction); a Z block
-// is one stored 1 KB block (one contiguous copy). Genotype words past n are
-// loaded from the row's start (any bytes do: they meet zero Z columns) and
-// rows past the range from the last row (their outputs are not stored). A
-// row-major genotype block at an 80-byte pitch (4 row segments per copy)
-// measured slower on MI355X: its 16-byte reads conflict on LDS banks.
+// into int8 digits (ZSlices). The genotype rows are first repacked on the
+// device (pack_u8_kernel) into 1 KB fragment blocks, 16 rows x 64 samples:
+// lane l of a block owns bytes 16 l .. 16 l + 15, samples 16 (l / 16) .. + 15
+// of row l % 16 (zero past n and past the rows). Z block (d, cb) holds for
+// lane l the same 16 samples of digit d of rotated index k0 + 16 cb + l % 16,
+// so both operands put sample s in the same MFMA slot; one MFMA per (digit,
+// SNP block, Z block) and 64-sample stage, exact int32 digit sums recombined
+// in FP64 by the epilogue. Both operands are loaded by direct global->LDS
+// copies, each block one contiguous 1 KB copy, into a ring of three stage
+// buffers two stages ahead of the MFMAs; each wave waits only for the stage it
+// is about to read (every wave issues the same number of copies per stage).
+// Copying genotype blocks of 16 row segments straight from the caller's rows
+// (4 bytes per lane, 16 rows x 16 bytes per instruction) measured slower on
+// MI355X at n = 1000, m = 1e6 (six digits 8.57 against 7.14 ms, four digits
+// 5.20 against 4.77, the repack included), and a row-major genotype block at
+// an 80-byte pitch slower still (its 16-byte reads conflict on LDS banks).
 template <int WM_, int WN_, int FM_, int FN_, int ND_ = kZSlices>
 struct RotI8L {
     static constexpr int WM = WM_, WN = WN_, FM = FM_, FN = FN_, ND = ND_;   // ND leading digits
     static constexpr int NW = WM * WN, NT = 64 * NW;
     static constexpr int TM = WM * FM * 16, TN = WN * FN * 16;
     static constexpr int AB = TM / 16, CB = TN / 16;
-    static constexpr int ABYTES = 1024;                  // genotype block: one fragment block
-    static constexpr int SBYTES = AB * ABYTES + ND * CB * 1024;   // genotype blocks, then Z (digit-major)
+    static constexpr int SBYTES = (AB + ND * CB) * 1024;   // genotype blocks, then Z (digit-major)
     static constexpr int NBUF = 3;
     static constexpr int LDS = NBUF * SBYTES;
-    static constexpr int AI = AB * (ABYTES / 256) / NW;  // genotype copies per wave and stage (256 B each)
-    static constexpr int ZI = ND * CB / NW;              // Z copies per wave and stage
+    static constexpr int AI = AB / NW;                   // genotype block copies per wave and stage
+    static constexpr int ZI = ND * CB / NW;              // Z block copies per wave and stage
     static constexpr int PER = AI + ZI;                  // copies per wave and stage
     static constexpr int NF = FM + ND * FN;              // fragments per wave and stage: genotype x, then (digit, y)
     static constexpr bool frag_is_b(int i) { return i >= FM; }
     static constexpr int frag_off(int i) {
-        return i < FM ? i * ABYTES : (((i - FM) / FN) * CB + (i - FM) % FN) * 1024;
+        return i < FM ? i * 1024 : (((i - FM) / FN) * CB + (i - FM) % FN) * 1024;
     }
-    static_assert(ABYTES % 256 == 0 && AB * (ABYTES / 256) % NW == 0 && ND * CB % NW == 0,
-                  "every wave issues the same copies");
+    static_assert(AB % NW == 0 && ND * CB % NW == 0, "every wave issues the same copies");
     static_assert(PER < 64 && SBYTES <= 65536 && LDS <= 160 * 1024, "rotation stage too large");
 };
 
 // fastest of sweeps on MI355X at n = 1000: 2 x 2 waves with six digits,
-// 2 x 4 waves (twice the rotated indices per genotype block) with four
+// 2 x 4 waves (twice the rotated indices per genotype block) with four; with
+// the repacked genotypes also against 2 x 4 waves of 4 x 1 and 4 x 2 waves of
+// 2 x 2 blocks (six digits: 9.0-9.2 against 7.1 ms at m = 1e6) and 2 x 2
+// waves of 8 x 1 blocks (10.0 ms); four digits 4 x 2 waves of 4 x 2 and 2 x 2,
+// 2 x 4 waves of 8 x 1 (5.0-5.4 against 4.8 ms)
 template <int ND>
 using DefaultRotI8L =
     typename std::conditional<ND == kZSlices, RotI8L<2, 2, 4, 1, ND>, RotI8L<2, 4, 4, 1, ND>>::type;
 
+// P: the packed genotype blocks of `rows` rows (pack_u8_kernel), at least
+// the tiles' rows (a multiple of TM) of them.
 template <class R>
-__global__ __launch_bounds__(R::NT) void rotate_u8_i8_lds_kernel(const uint8_t *__restrict__ X, int64_t rows, int n,
-                                                                 int64_t ldx, ZSlices zs, int n_pad, RotOut out) {
+__global__ __launch_bounds__(R::NT) void rotate_u8_i8_lds_kernel(const uint8_t *__restrict__ P, int64_t rows, int n,
+                                                                 ZSlices zs, int n_pad, RotOut out) {
     constexpr int TN = R::TN, FM = R::FM, FN = R::FN, ND = R::ND, CB = R::CB, AB = R::AB;
     extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
     const int ntn = n_pad / TN;
@@ -389,20 +231,12 @@ __global__ __launch_bounds__(R::NT) void rotate_u8_i8_lds_kernel(const uint8_t *
     const int g = lane >> 4;
     const int nst = (n + 63) / 64;   // stages of 64 samples; 64 nst <= n_pad
 
-    // genotype copy u of this wave: part j of block rb (q = wave + u NW,
-    // rb = q / 4, j = q % 4) fills block bytes [256 j, 256 j + 256), i.e. for
-    // lane l the word of row 16 rb + l / 4 at samples 16 j + 4 (l % 4) .. + 3
+    // genotype copy u of this wave: block rb = wave + u NW of the tile, one
+    // contiguous 1 KB block per stage
     const uint8_t *asrc[R::AI];
-    int aoff[R::AI], adst[R::AI];
 #pragma unroll
-    for (int u = 0; u < R::AI; ++u) {
-        const int q = wave + u * R::NW, rb = q / 4, j = q % 4;
-        int64_t i = i_base + rb * 16 + lane / 4;
-        if (i >= rows) i = rows - 1;
-        asrc[u] = X + i * ldx;
-        aoff[u] = 16 * j + 4 * (lane % 4);
-        adst[u] = rb * R::ABYTES + 256 * j;
-    }
+    for (int u = 0; u < R::AI; ++u)
+        asrc[u] = P + ((i_base / 16 + wave + u * R::NW) * (int64_t)(n_pad / 64)) * 1024 + 16 * lane;
     // Z copy u: block b = d CB + cb holds for lane l the 16 bytes of digit d,
     // row k0 + 16 cb + l % 16, samples 16 (l / 16) .. + 15 (one stored block)
     const int8_t *zsrc[R::ZI];
@@ -411,15 +245,12 @@ __global__ __launch_bounds__(R::NT) void rotate_u8_i8_lds_kernel(const uint8_t *
     for (int u = 0; u < R::ZI; ++u) {
         const int b = wave + u * R::NW, d = b / CB, cb = b % CB;
         zsrc[u] = zs.q + ((int64_t)d * (n_pad / 16) + k_base / 16 + cb) * (n_pad / 64) * 1024 + 16 * lane;
-        zdst[u] = AB * R::ABYTES + b * 1024;
+        zdst[u] = AB * 1024 + b * 1024;
     }
     auto issue = [&](int c) {
         uint8_t *buf = lds + (c % R::NBUF) * R::SBYTES;
 #pragma unroll
-        for (int u = 0; u < R::AI; ++u) {
-            const int s = c * 64 + aoff[u];
-            lds_dma4(asrc[u] + (s < n ? s : 0), buf + adst[u]);
-        }
+        for (int u = 0; u < R::AI; ++u) lds_dma16(asrc[u] + (int64_t)c * 1024, buf + (wave + u * R::NW) * 1024);
 #pragma unroll
         for (int u = 0; u < R::ZI; ++u) lds_dma16((const uint8_t *)(zsrc[u] + (int64_t)c * 1024), buf + zdst[u]);
     };
@@ -434,8 +265,8 @@ __global__ __launch_bounds__(R::NT) void rotate_u8_i8_lds_kernel(const uint8_t *
 
     issue(0);
     if (nst > 1) issue(1);
-    const uint32_t sa = lds_addr(lds) + lane * 16 + wm * FM * R::ABYTES;
-    const uint32_t sz = lds_addr(lds) + lane * 16 + AB * R::ABYTES + wn * FN * 1024;
+    const uint32_t sa = lds_addr(lds) + lane * 16 + wm * FM * 1024;
+    const uint32_t sz = lds_addr(lds) + lane * 16 + AB * 1024 + wn * FN * 1024;
     for (int c = 0; c < nst; ++c) {
         // this wave's copies of stage c landed; those of stage c + 1 may be in flight
         if (c + 1 < nst) __builtin_amdgcn_s_waitcnt(vmcnt_imm(R::PER));
@@ -558,34 +389,45 @@ hipError_t launch_rotate_t(const void *X, int dtype, int64_t rows, int n, int64_
     return hipGetLastError();
 }
 
+// Genotype rows -> fragment blocks for rotate_u8_i8_lds_kernel: block
+// (rg, c) = rows 16 rg .. + 15, samples 64 c .. + 63, at P + (rg (n_pad / 64)
+// + c) KB; thread t writes the 16 bytes of lane t % 64 of block t / 64 (zero
+// past n and past `rows`). Rows, stride and base aligned to 4 bytes (aligned4)
+// are read a word at a time, any others byte by byte.
+__global__ void pack_u8_kernel(const uint8_t *__restrict__ X, int64_t rows, int n, int64_t ldx, int n_pad,
+                               int64_t units, uint8_t *__restrict__ P, int aligned4) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= units) return;
+    const int l = (int)(t & 63);
+    const int64_t blk = t >> 6;
+    const int nkb = n_pad / 64;
+    const int c = (int)(blk % nkb);
+    const int64_t row = (blk / nkb) * 16 + (l & 15);
+    const int s0 = c * 64 + 16 * (l >> 4);
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    if (row < rows) {
+        const uint8_t *src = X + row * ldx;
+        if (aligned4) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (s0 + 4 * q < n) w[q] = *(const uint32_t *)(src + s0 + 4 * q);   // n % 4 == 0
+        } else {
+            for (int e = 0; e < 16; ++e)
+                if (s0 + e < n) w[e >> 2] |= (uint32_t)src[s0 + e] << (8 * (e & 3));
+        }
+    }
+    *(uint4 *)(P + t * 16) = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// Rows in chunks of zs.pack_rows: pack the chunk into zs.pack, rotate it.
 template <class R>
 hipError_t launch_rotate_u8_i8_t(const uint8_t *X, int64_t rows, int n, int64_t ldx, const ZSlices &zs, int n_pad,
                                  const RotOut &out, hipStream_t s) {
     if (rows <= 0) return hipSuccess;
-    if (n_pad % R::TN || n_pad % 64 || n > n_pad || n_pad > kZSliceMaxNpad) return hipErrorInvalidValue;
-    const int64_t tiles = ((rows + R::TM - 1) / R::TM) * (n_pad / R::TN);
-    if (R::LDS > 65536) {
-        static bool attr_set = false;   // per instantiation
-        if (!attr_set) {
-            hipError_t e = hipFuncSetAttribute((const void *)rotate_u8_i8_kernel<R>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, R::LDS);
-            if (e != hipSuccess) return e;
-            attr_set = true;
-        }
-    }
-    hipLaunchKernelGGL((rotate_u8_i8_kernel<R>), dim3((unsigned)tiles), dim3(R::NT), R::LDS, s, X, rows, n, ldx, zs,
-                       n_pad, out);
-    return hipGetLastError();
-}
-
-template <class R>
-hipError_t launch_rotate_u8_i8_lds_t(const uint8_t *X, int64_t rows, int n, int64_t ldx, const ZSlices &zs,
-                                     int n_pad, const RotOut &out, hipStream_t s) {
-    if (rows <= 0) return hipSuccess;
-    if (n_pad % R::TN || n_pad % 64 || n > n_pad || n_pad > kZSliceMaxNpad || n % 4 || ldx % 4 ||
-        ((uintptr_t)X) % 4)
+    if (n_pad % R::TN || n_pad % 64 || n > n_pad || n_pad > kZSliceMaxNpad || !zs.pack || zs.pack_rows <= 0 ||
+        zs.pack_rows % 256)
         return hipErrorInvalidValue;
-    const int64_t tiles = ((rows + R::TM - 1) / R::TM) * (n_pad / R::TN);
+    static_assert(256 % R::TM == 0, "a chunk of whole tiles");
     if (R::LDS > 65536) {
         static bool attr_set = false;   // per instantiation
         if (!attr_set) {
@@ -595,8 +437,18 @@ hipError_t launch_rotate_u8_i8_lds_t(const uint8_t *X, int64_t rows, int n, int6
             attr_set = true;
         }
     }
-    hipLaunchKernelGGL((rotate_u8_i8_lds_kernel<R>), dim3((unsigned)tiles), dim3(R::NT), R::LDS, s, X, rows, n, ldx,
-                       zs, n_pad, out);
+    const int aligned4 = (n % 4 == 0 && ldx % 4 == 0 && ((uintptr_t)X) % 4 == 0) ? 1 : 0;
+    for (int64_t r0 = 0; r0 < rows; r0 += zs.pack_rows) {
+        const int64_t cnt = std::min(zs.pack_rows, rows - r0);
+        const int64_t units = (cnt + R::TM - 1) / R::TM * R::TM / 16 * (n_pad / 64) * 64;   // <= pack_rows n_pad / 16
+        hipLaunchKernelGGL(pack_u8_kernel, dim3((unsigned)((units + 255) / 256)), dim3(256), 0, s, X + r0 * ldx, cnt,
+                           n, ldx, n_pad, units, zs.pack, aligned4);
+        RotOut o = out;
+        o.row0 += r0;
+        const int64_t tiles = ((cnt + R::TM - 1) / R::TM) * (n_pad / R::TN);
+        hipLaunchKernelGGL((rotate_u8_i8_lds_kernel<R>), dim3((unsigned)tiles), dim3(R::NT), R::LDS, s,
+                           (const uint8_t *)zs.pack, cnt, n, zs, n_pad, o);
+    }
     return hipGetLastError();
 }
 
@@ -604,18 +456,13 @@ hipError_t launch_rotate(const void *X, int dtype, int64_t rows, int n, int64_t 
                          int n_pad, const RotOut &out, hipStream_t s, const ZSlices *zs) {
     // all digits when an FP64 store is written, the leading ones otherwise
     const bool full = out.f64 != nullptr;
-    if (dtype == GWAS_DT_U8 && zs && zs->q && n_pad <= kZSliceMaxNpad && n_pad % DefaultRotI8L<kZSlices>::TN == 0 &&
-        n_pad % DefaultRotI8L<kZSlicesShort>::TN == 0 && n % 4 == 0 && ldx % 4 == 0 && ((uintptr_t)X) % 4 == 0)
-        return full ? launch_rotate_u8_i8_lds_t<DefaultRotI8L<kZSlices>>((const uint8_t *)X, rows, n, ldx, *zs,
-                                                                         n_pad, out, s)
-                    : launch_rotate_u8_i8_lds_t<DefaultRotI8L<kZSlicesShort>>((const uint8_t *)X, rows, n, ldx,
-                                                                              *zs, n_pad, out, s);
-    if (dtype == GWAS_DT_U8 && zs && zs->q && n_pad <= kZSliceMaxNpad && n_pad % DefaultRotI8<kZSlices>::TN == 0)
-        return full ? launch_rotate_u8_i8_t<DefaultRotI8<kZSlices>>((const uint8_t *)X, rows, n, ldx, *zs, n_pad,
-                                                                    out, s)
-                    : launch_rotate_u8_i8_t<DefaultRotI8<kZSlicesShort>>((const uint8_t *)X, rows, n, ldx, *zs,
-                                                                         n_pad, out, s);
-    if (dtype == GWAS_DT_U8) return hipErrorInvalidValue;   // needs the digits of Z
+    if (dtype == GWAS_DT_U8 && zs && zs->q && zs->pack && n_pad <= kZSliceMaxNpad &&
+        n_pad % DefaultRotI8L<kZSlices>::TN == 0 && n_pad % DefaultRotI8L<kZSlicesShort>::TN == 0)
+        return full ? launch_rotate_u8_i8_t<DefaultRotI8L<kZSlices>>((const uint8_t *)X, rows, n, ldx, *zs, n_pad,
+                                                                     out, s)
+                    : launch_rotate_u8_i8_t<DefaultRotI8L<kZSlicesShort>>((const uint8_t *)X, rows, n, ldx, *zs,
+                                                                          n_pad, out, s);
+    if (dtype == GWAS_DT_U8) return hipErrorInvalidValue;   // needs the digits of Z and the pack buffer
     const int64_t wgs = ((rows + DefaultRot::TM - 1) / DefaultRot::TM) * (n_pad / DefaultRot::TN);
     if (wgs < 1024 && n_pad % SmallRot::TN == 0)   // fewer than 4 workgroups per CU
         return launch_rotate_t<SmallRot>(X, dtype, rows, n, ldx, Zrows, n_pad, out, s);

@@ -33,7 +33,8 @@ class Options(ctypes.Structure):
                 ("device", ctypes.c_int32), ("max_traits", ctypes.c_int32),
                 ("slab_snps", ctypes.c_int32), ("f32_flush", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("ring_slots", ctypes.c_int32),
-                ("host_threads", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("host_threads", ctypes.c_int32), ("geno_chunk_snps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class Slab(ctypes.Structure):
@@ -209,7 +210,7 @@ class Cohort:
     def __init__(self, Z, w, xl, m_capacity: int, forms=("f64", "f32", "bf16x3"),
                  max_traits: int = 1024, device: int = 0, slab_snps: int = 0,
                  f32_flush: int | None = None, timing: bool = False, ring_slots: int = 0,
-                 host_threads: int = 0):
+                 host_threads: int = 0, geno_chunk_snps: int = 0):
         lib = load()
         Z = np.asarray(Z, dtype=np.float64)
         n = Z.shape[0]
@@ -231,6 +232,7 @@ class Cohort:
         opt.timing = int(bool(timing))
         opt.ring_slots = int(ring_slots)
         opt.host_threads = int(host_threads)
+        opt.geno_chunk_snps = int(geno_chunk_snps)
         h = ctypes.c_void_p()
         _check(lib.gwas_setup(ctypes.byref(h), n, xl.shape[0] + 1, zc.ctypes.data, w.ctypes.data,
                               xl.ctypes.data, ctypes.byref(opt)))

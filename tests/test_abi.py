@@ -61,6 +61,19 @@ def test_setup_rejects_fold_intervals_other_than_0_and_2(bad):
         gwas.Cohort(z, w, xl, 4, forms=("f32",), f32_flush=bad)
 
 
+@pytest.mark.parametrize("bad", [-256, 100, 257])
+def test_setup_rejects_genotype_chunks_not_a_multiple_of_256(bad):
+    """geno_chunk_snps is checked with the other options, before any device call."""
+    import numpy as np
+
+    from paper_1210_7683_amd import gwas
+    if not os.path.exists(gwas.LIB_PATH):
+        pytest.fail("libgwas.so is not built; run python -m paper_1210_7683_amd.build")
+    n = 8
+    with pytest.raises(gwas.GwasError, match="geno_chunk_snps"):
+        gwas.Cohort(np.eye(n), np.ones(n), np.ones((1, n)), 4, forms=("f32",), geno_chunk_snps=bad)
+
+
 @pytest.mark.parametrize("n", [0, -3, 16385])
 def test_eigh_rejects_sizes_out_of_range(n):
     """gwas_eigh checks n before it opens the solver or touches a device."""

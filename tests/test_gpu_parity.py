@@ -83,13 +83,17 @@ def test_rotate_dtypes_and_device_input(tiny, dtype, torch_cuda):
 
 
 @pytest.mark.parametrize("full", [True, False])
-@pytest.mark.parametrize("n,m,shift", [(1000, 300, 0), (333, 257, 0), (1000, 300, 1), (64, 17, 0),
-                                       (600, 1100, 0), (600, 1100, 1)])
-def test_genotype_rotation_full_byte_range(n, m, shift, full, torch_cuda):
+@pytest.mark.parametrize("n,m,shift,chunk", [(1000, 300, 0, 0), (333, 257, 0, 0), (1000, 300, 1, 0), (64, 17, 0, 0),
+                                             (600, 1100, 0, 0), (600, 1100, 1, 0), (1000, 700, 0, 256),
+                                             (333, 1100, 1, 512)])
+def test_genotype_rotation_full_byte_range(n, m, shift, chunk, full, torch_cuda):
     """Genotype bytes over the whole range 0..255 (the int8 kernels offset them
     to v - 128 and sum exact int32 digit products): every rotated value against
-    the FP64 product. n = 1000 takes the LDS-staged kernel; n = 333, and rows
-    starting at an odd device address (shift = 1), the register-staged one.
+    the FP64 product. The rows are repacked on the device before the int8
+    kernel: a word at a time where n, the stride and the address are multiples
+    of 4 (n = 1000, 600, 64), byte by byte for n = 333 and for rows starting at
+    an odd device address (shift = 1). chunk > 0 repacks that many rows at a
+    time (geno_chunk_snps), so several chunks and a ragged last one are taken.
     n = 600, m = 1100: 10 or 20 column tiles and 9 row tiles, so the tile order's
     tail (column tiles past the last multiple of 8, by groups of 8 row tiles)
     and its partial group are taken.
@@ -103,7 +107,7 @@ def test_genotype_rotation_full_byte_range(n, m, shift, full, torch_cuda):
     xr[1] = 0
     w, z = np.linalg.eigh(phi)
     from paper_1210_7683_amd import gwas
-    c = gwas.Cohort(z, w, xl, m, forms=("f64", "f32") if full else ("f32",))
+    c = gwas.Cohort(z, w, xl, m, forms=("f64", "f32") if full else ("f32",), geno_chunk_snps=chunk)
     buf = torch.zeros(m * n + shift, dtype=torch.uint8, device="cuda")
     dev = buf[shift:].view(m, n)
     dev.copy_(torch.from_numpy(xr))
@@ -117,7 +121,8 @@ def test_genotype_rotation_full_byte_range(n, m, shift, full, torch_cuda):
         assert np.array_equal(c.copy_rotated(0, m, "f32"), got.astype(np.float32))
     else:
         err = np.abs(c.copy_rotated(0, m, "f32").astype(np.float64) - ref).max() / np.abs(ref).max()
-    print("n=%d m=%d shift=%d full=%d: max |rotated - FP64 product| / max = %.2e" % (n, m, shift, full, err))
+    print("n=%d m=%d shift=%d chunk=%d full=%d: max |rotated - FP64 product| / max = %.2e" % (
+        n, m, shift, chunk, full, err))
     assert err <= (1e-12 if full else 1e-7)
     c.close()
 
