@@ -40,10 +40,13 @@ def collect(c, xr, y, h2, form, **kw):
 
 
 @pytest.mark.parametrize("form", FORMS)
-@pytest.mark.parametrize("n,p,m,t,cap,slab,traits", [(200, 4, 1000, 7, 256, 64, 1024),
-                                                      (77, 3, 301, 40, 64, 16, 16),
-                                                      (130, 5, 250, 2, 100, 32, 1024)])
-def test_streamed_snps_equal_resident_solve(form, n, p, m, t, cap, slab, traits, torch_cuda):
+@pytest.mark.parametrize("n,p,m,t,cap,slab,traits,chunk", [(200, 4, 1000, 7, 256, 64, 1024, 0),
+                                                            (77, 3, 301, 40, 64, 16, 16, 0),
+                                                            (130, 5, 250, 2, 100, 32, 1024, 0),
+                                                            (200, 4, 1500, 7, 1024, 64, 1024, 256)])
+def test_streamed_snps_equal_resident_solve(form, n, p, m, t, cap, slab, traits, chunk, torch_cuda):
+    """chunk > 0: the genotype blocks (cap / 2 SNPs) are repacked and rotated
+    chunk SNPs at a time on the library's second stream (geno_chunk_snps)."""
     torch = torch_cuda
     phi, xl, xr, y, h2 = synth.small(n, p, m, t, seed=n + m + t)
     ref_c = cohort(phi, xl, xr, forms=(form,), max_traits=traits)
@@ -51,7 +54,7 @@ def test_streamed_snps_equal_resident_solve(form, n, p, m, t, cap, slab, traits,
     ref_c.close()
     w, z = np.linalg.eigh(phi)
     from paper_1210_7683_amd import gwas
-    c = gwas.Cohort(z, w, xl, cap, forms=(form,), slab_snps=slab, max_traits=traits)
+    c = gwas.Cohort(z, w, xl, cap, forms=(form,), slab_snps=slab, max_traits=traits, geno_chunk_snps=chunk)
     host = torch.from_numpy(xr).pin_memory()
     b, sums = collect(c, host, y, h2, form)
     assert np.array_equal(b, full)
