@@ -99,11 +99,13 @@ typedef struct gwas_stats_t {
     int64_t resident_bytes; /* device memory held by the context                       */
     int64_t fused_launches; /* timed launches of the fused kernel (timing option)        */
     double fused_ms;        /* their summed duration, ms                                 */
-    int64_t rotate_launches;/* timed launches of the rotation kernel                     */
+    int64_t rotate_launches;/* timed rotations: per device block of gwas_rotate (and per
+                               streamed SNP block), the repack and int8 launches of
+                               its chunks together                                     */
     double rotate_ms;       /* their summed duration, ms                                 */
     int64_t dot_launches;   /* launches of the dot-product kernel: FP64 and FP32 solve
                                calls with at most 3 traits (whose (p+1) x t x n_pad
-                               panels fit 64 KB) use it instead of the MFMA tiles      */
+                               panels fit 160 KB) use it instead of the MFMA tiles     */
     int64_t reserved[5];
 } gwas_stats_t;
 
