@@ -127,6 +127,30 @@ def test_genotype_rotation_full_byte_range(n, m, shift, chunk, full, torch_cuda)
     c.close()
 
 
+def test_genotype_rotation_in_pieces_at_offsets(torch_cuda):
+    """Genotype blocks rotated into the middle of the store, in repack chunks of
+    256 SNPs (chunk offsets add to the block's first row), give the same store,
+    bitwise, as one call over all SNPs; both against the FP64 product."""
+    torch = torch_cuda
+    n, m = 333, 1100
+    phi, xl, _, _, _ = synth.small(n, 3, 1, 1, seed=8)
+    xr = np.random.default_rng(9).integers(0, 256, size=(m, n), dtype=np.uint8)
+    w, z = np.linalg.eigh(phi)
+    from paper_1210_7683_amd import gwas
+    whole = gwas.Cohort(z, w, xl, m, forms=("f64",), geno_chunk_snps=256)
+    whole.rotate(0, torch.from_numpy(xr).cuda())
+    pieces = gwas.Cohort(z, w, xl, m, forms=("f64",), geno_chunk_snps=256)
+    for a, b in [(700, 1100), (0, 300), (300, 700)]:   # out of order, each spanning chunks
+        pieces.rotate(a, torch.from_numpy(np.ascontiguousarray(xr[a:b])).cuda())
+    torch.cuda.synchronize()
+    got_whole, got_pieces = whole.copy_rotated(0, m, "f64"), pieces.copy_rotated(0, m, "f64")
+    whole.close()
+    pieces.close()
+    assert np.array_equal(got_whole, got_pieces)
+    ref = xr.astype(np.float64) @ z
+    assert np.abs(got_pieces - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("form", ["f64", "f32"])
 def test_full_byte_range_genotypes_solve_against_oracle(form, torch_cuda):
     """b for genotype bytes over 0..255 (dosages scaled to a byte, say) against
