@@ -164,9 +164,10 @@ __global__ __launch_bounds__(R::NT) void rotate_kernel(const Tin *__restrict__ X
 
 // Genotype rotation on the int8 MFMAs (v_mfma_i32_16x16x64_i8) with Z sliced
 // into int8 digits (ZSlices). The genotype rows are first repacked on the
-// device (pack_u8_kernel) into 1 KB fragment blocks, 16 rows x 64 samples:
-// lane l of a block owns bytes 16 l .. 16 l + 15, samples 16 (l / 16) .. + 15
-// of row l % 16 (zero past n and past the rows). Z block (d, cb) holds for
+// device (pack_u8_kernel) into 1 KB fragment blocks, 16 rows x 64 samples, as
+// signed bytes v - 128: lane l of a block owns bytes 16 l .. 16 l + 15, samples
+// 16 (l / 16) .. + 15 of row l % 16 (-128 past n and past the rows: they meet
+// zero Z columns or feed outputs that are not stored). Z block (d, cb) holds for
 // lane l the same 16 samples of digit d of rotated index k0 + 16 cb + l % 16,
 // so both operands put sample s in the same MFMA slot; one MFMA per (digit,
 // SNP block, Z block) and 64-sample stage, exact int32 digit sums recombined
@@ -279,11 +280,6 @@ __global__ __launch_bounds__(R::NT) void rotate_u8_i8_lds_kernel(const uint8_t *
         const uint32_t so = (c % R::NBUF) * R::SBYTES;
         i4v f[R::NF];
         lds_read_frags<R, 0, R::NF>(f, sa + so, sz + so);
-        i4v av[FM];
-#pragma unroll
-        for (int x = 0; x < FM; ++x)   // byte v -> signed v - 128
-            av[x] = i4v{f[x][0] ^ (int)0x80808080u, f[x][1] ^ (int)0x80808080u, f[x][2] ^ (int)0x80808080u,
-                        f[x][3] ^ (int)0x80808080u};
 #pragma unroll
         for (int d = 0; d < ND; ++d)
 #pragma unroll
@@ -291,7 +287,7 @@ __global__ __launch_bounds__(R::NT) void rotate_u8_i8_lds_kernel(const uint8_t *
 #pragma unroll
                 for (int x = 0; x < FM; ++x)
                     acc[d][x][y] =
-                        __builtin_amdgcn_mfma_i32_16x16x64_i8(av[x], f[FM + d * FN + y], acc[d][x][y], 0, 0, 0);
+                        __builtin_amdgcn_mfma_i32_16x16x64_i8(f[x], f[FM + d * FN + y], acc[d][x][y], 0, 0, 0);
     }
 
     const int l16 = lane & 15;
@@ -391,9 +387,10 @@ hipError_t launch_rotate_t(const void *X, int dtype, int64_t rows, int n, int64_
 
 // Genotype rows -> fragment blocks for rotate_u8_i8_lds_kernel: block
 // (rg, c) = rows 16 rg .. + 15, samples 64 c .. + 63, at P + (rg (n_pad / 64)
-// + c) KB; thread t writes the 16 bytes of lane t % 64 of block t / 64 (zero
-// past n and past `rows`). Rows, stride and base aligned to 4 bytes (aligned4)
-// are read a word at a time, any others byte by byte.
+// + c) KB; thread t writes the 16 bytes of lane t % 64 of block t / 64 as
+// signed bytes v - 128 (byte v XOR 0x80; -128 past n and past `rows`). Rows,
+// stride and base aligned to 4 bytes (aligned4) are read a word at a time,
+// any others byte by byte.
 __global__ void pack_u8_kernel(const uint8_t *__restrict__ X, int64_t rows, int n, int64_t ldx, int n_pad,
                                int64_t units, uint8_t *__restrict__ P, int aligned4) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -416,7 +413,7 @@ __global__ void pack_u8_kernel(const uint8_t *__restrict__ X, int64_t rows, int 
                 if (s0 + e < n) w[e >> 2] |= (uint32_t)src[s0 + e] << (8 * (e & 3));
         }
     }
-    *(uint4 *)(P + t * 16) = make_uint4(w[0], w[1], w[2], w[3]);
+    *(uint4 *)(P + t * 16) = make_uint4(w[0] ^ 0x80808080u, w[1] ^ 0x80808080u, w[2] ^ 0x80808080u, w[3] ^ 0x80808080u);
 }
 
 // Rows in chunks of zs.pack_rows: pack the chunk into zs.pack, rotate it.
